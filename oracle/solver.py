@@ -1,0 +1,191 @@
+"""Residual, time step, Runge-Kutta update and wall-pressure objective.
+
+* Residual: finite-volume form of eq. (1), Sec. 2, inviscid part with no
+  source: for every cell, R = (1/Omega) sum over its faces of the outward
+  numerical flux times area, so that dQ/dt = -R.  Faces are visited one index
+  direction at a time: MUSCL face states (muscl.face_states) and the Roe flux
+  (roe.roe_flux) on every face of the direction, then the flux difference.
+* Wall faces: Sec. 7.2 V7 overwrites the Riemann flux on wall faces after the
+  boundary enforcement.  Reading: F = (0, p_w S, 0) with the wall pressure
+  extrapolated linearly in index space, p_w = 1.5 p_0 - 0.5 p_1 (p_0 the cell
+  adjacent to the wall, p_1 the next one in).
+* Time step: the paper does not state it.  Reading: a global step
+  dt = CFL * min over all cells of Omega / lambda, with
+  lambda = sum_d (|u . Sbar_d| + c |Sbar_d|), Sbar_d the mean of the cell's
+  two area vectors in direction d, evaluated once per step from Q^n.
+* Runge-Kutta: Sec. 2, the explicit M-step scheme of Jameson, Schmidt and
+  Turkel: Q^(k) = Q^(0) - alpha_k dt R(Q^(k-1)), alpha_k = 1/(M - k + 1).
+* Objective: J = sum over slip-wall faces of p_w |S| (integrated wall pressure).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import gas, metrics as metrics_mod, muscl, roe
+from .ghosts import face_area_slab, fill_ghosts, interior_layer, tangential_axes, tensor_axis
+
+F64 = torch.float64
+
+
+class _Patch:
+    def __init__(self, p, index):
+        self.block, self.face, self.lo, self.hi, self.kind = p.block, p.face, list(p.lo), list(p.hi), p.kind
+        self.index = index
+
+
+class Problem:
+    """Blocks, topology and scheme of a ``synth.Case`` as oracle tensors.
+
+    ``nodes`` and the inflow parameters are leaf tensors so gradients with
+    respect to them can be taken with torch.autograd."""
+
+    def __init__(self, case, requires_grad=False):
+        self.case = case
+        self.dim = case.dim
+        self.nvar = case.dim + 2
+        sch = case.scheme
+        self.gamma = sch.gamma
+        self.limiter = sch.limiter
+        self.eps = sch.muscl_eps
+        self.kappa = sch.muscl_kappa
+        self.efix = sch.efix
+        self.stages = sch.rk_stages
+        self.cfl = sch.cfl
+        self.dt_fixed = sch.dt_fixed
+        le = sch.lim_eps if sch.lim_eps is not None else [0.0] * self.nvar
+        self.lim_eps2 = torch.tensor([e * e for e in le], dtype=F64)
+        self.nodes = [torch.tensor(b.nodes, dtype=F64, requires_grad=requires_grad) for b in case.blocks]
+        self.conns = case.conns
+        self.bcs = []
+        self.bc_params = []
+        for p in case.bcs:
+            self.bcs.append(_Patch(p, len(self.bc_params) if p.kind == "sup_inflow" else -1))
+            if p.kind == "sup_inflow":
+                self.bc_params.append(torch.tensor(p.params, dtype=F64, requires_grad=requires_grad))
+
+    # -- grid ---------------------------------------------------------------
+    def metrics(self):
+        return [metrics_mod.metrics(X) for X in self.nodes]
+
+    # -- state conversions --------------------------------------------------
+    def initial_state(self):
+        return [gas.cons_from_prim(torch.tensor(q, dtype=F64), self.gamma) for q in self.case.prims]
+
+    # -- residual -----------------------------------------------------------
+    def block_residual_padded(self, qpad, S, vol, walls=()):
+        """Residual of one block from a padded primitive array (ghosts given)."""
+        dim = self.dim
+        nd = qpad.ndim
+        eps2 = self.lim_eps2.reshape([-1] + [1] * (nd - 1))
+        div = 0.0
+        for d in range(dim):
+            ax = tensor_axis(nd, d)
+            # interior range in the other directions, full padded range along d
+            sl = [slice(None)] * nd
+            for a in range(dim):
+                if a != d:
+                    sl[tensor_axis(nd, a)] = slice(2, -2)
+            qd = qpad[tuple(sl)]
+            qL, qR = muscl.face_states(qd, ax, self.limiter, self.eps, self.kappa, eps2)
+            F = roe.roe_flux(qL, qR, S[d], self.gamma, self.efix)
+            for (face, lo, hi) in walls:
+                if face // 2 != d:
+                    continue
+                F = self._wall_override(F, qpad, S[d], face, lo, hi)
+            n = F.shape[ax] - 1
+            div = div + (F.narrow(ax, 1, n) - F.narrow(ax, 0, n))
+        return div / vol
+
+    def _wall_override(self, F, qpad, Sd, face, lo, hi):
+        dim, nd = self.dim, F.ndim
+        ax = tensor_axis(nd, face // 2)
+        q = qpad[tuple([slice(None)] + [slice(2, -2)] * dim)]
+        p0 = interior_layer(q, dim, face, 0, lo, hi)[-1]
+        p1 = interior_layer(q, dim, face, 1, lo, hi)[-1]
+        pw = 1.5 * p0 - 0.5 * p1
+        sl = [slice(None)] * nd
+        sl[ax] = 0 if face % 2 == 0 else F.shape[ax] - 1
+        for t, a in enumerate(tangential_axes(dim, face)):
+            sl[tensor_axis(nd, a)] = slice(lo[t], hi[t])
+        Sf = Sd[tuple(sl)]
+        if dim == 3:
+            Sf = Sf.permute(0, 2, 1)  # to (dim, t1, t2) like pw
+        mom = pw[None] * Sf
+        zero = torch.zeros_like(pw)[None]
+        Fw = torch.cat([zero, mom, zero])
+        if dim == 3:
+            Fw = Fw.permute(0, 2, 1)
+        F = F.clone()
+        F[tuple(sl)] = Fw
+        return F
+
+    def walls_of(self, b):
+        return [(p.face, p.lo, p.hi) for p in self.bcs if p.block == b and p.kind == "slip_wall"]
+
+    def residual(self, Q_list, met=None):
+        met = self.metrics() if met is None else met
+        q_list = [gas.prim_from_cons(Q, self.gamma) for Q in Q_list]
+        S_list = [m[0] for m in met]
+        pads = fill_ghosts(self, q_list, S_list)
+        return [self.block_residual_padded(pads[b], met[b][0], met[b][1], self.walls_of(b))
+                for b in range(len(Q_list))]
+
+    # -- time step ----------------------------------------------------------
+    def cell_dt(self, Q, S, vol):
+        """Omega / lambda per cell."""
+        q = gas.prim_from_cons(Q, self.gamma)
+        c = gas.sound_speed(q, self.gamma)
+        vel = q[1:-1]
+        lam = 0.0
+        for d in range(self.dim):
+            Sd = S[d]
+            n = Sd.shape[tensor_axis(Sd.ndim, d)] - 1
+            axS = tensor_axis(Sd.ndim, d)
+            Sbar = 0.5 * (Sd.narrow(axS, 0, n) + Sd.narrow(axS, 1, n))
+            lam = lam + (vel * Sbar).sum(0).abs() + c * torch.sqrt((Sbar * Sbar).sum(0))
+        return vol / lam
+
+    def time_step(self, Q_list, met=None):
+        if self.dt_fixed is not None:
+            return torch.tensor(self.dt_fixed, dtype=F64)
+        met = self.metrics() if met is None else met
+        m = min(self.cell_dt(Q, met[b][0], met[b][1]).min() for b, Q in enumerate(Q_list))
+        return self.cfl * m
+
+    # -- Runge-Kutta --------------------------------------------------------
+    def rk_step(self, Q_list, met=None, dt=None, residual_fn=None):
+        met = self.metrics() if met is None else met
+        dt = self.time_step(Q_list, met) if dt is None else dt
+        res = (lambda Qs: self.residual(Qs, met)) if residual_fn is None else residual_fn
+        M = self.stages
+        Q0 = Q_list
+        Qk = Q_list
+        for k in range(1, M + 1):
+            alpha = 1.0 / (M - k + 1)
+            R = res(Qk)
+            Qk = [Q0[b] - alpha * dt * R[b] for b in range(len(Q0))]
+        return Qk, dt
+
+    def run(self, Q_list, steps, met=None):
+        met = self.metrics() if met is None else met
+        dts = []
+        for _ in range(steps):
+            Q_list, dt = self.rk_step(Q_list, met)
+            dts.append(dt)
+        return Q_list, dts
+
+    # -- objective ----------------------------------------------------------
+    def wall_pressure_integral(self, Q_list, met=None):
+        met = self.metrics() if met is None else met
+        J = torch.zeros((), dtype=F64)
+        for p in self.bcs:
+            if p.kind != "slip_wall":
+                continue
+            q = gas.prim_from_cons(Q_list[p.block], self.gamma)
+            p0 = interior_layer(q, self.dim, p.face, 0, p.lo, p.hi)[-1]
+            p1 = interior_layer(q, self.dim, p.face, 1, p.lo, p.hi)[-1]
+            pw = 1.5 * p0 - 0.5 * p1
+            S = met[p.block][0][p.face // 2]
+            Sf = face_area_slab(S, self.dim, p.face, p.lo, p.hi)
+            J = J + (pw * torch.sqrt((Sf * Sf).sum(0))).sum()
+        return J
