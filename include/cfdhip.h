@@ -1,0 +1,200 @@
+/*
+ * cfdhip -- FP64 structured multi-block Euler hot path for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libcfdhip.so.  Every entry point takes plain pointers and sizes.
+ * Pointers named dev_* are device memory on the GPU that was current when the
+ * context was created; pointers named *_host are host memory.  The caller
+ * owns every buffer it passes; the library never keeps a caller pointer
+ * beyond the call except the bound workspace (cfd_bind_workspace).
+ *
+ * Method (arXiv 2012.02925, "An Improved Framework of GPU Computing for CFD
+ * Applications on Structured Grids using OpenACC"):
+ *   - finite-volume form of the Euler equations (Sec. 2, eq. (1)-(2));
+ *   - MUSCL reconstruction of primitive variables with a limiter
+ *     (Sec. 7.2, V4, eq. (flux)), Roe flux-difference splitting in each index
+ *     direction (Sec. 2), flux divergence on curvilinear metrics;
+ *   - wall-face flux override (Sec. 7.2, V7);
+ *   - ghost cells for physical and connected boundaries, connected ghosts
+ *     exchanged by device pack/unpack at every Runge-Kutta stage
+ *     (Sec. 2, Sec. 4, Sec. 7.2 V1/V5);
+ *   - explicit M-stage Runge-Kutta time marching (Sec. 2), global CFL step.
+ *
+ * Layouts used at this boundary
+ *   State / residual ("packed"): FP64 structure of arrays,
+ *     [var][cell], var = 0..dim+1, cells of all blocks concatenated in block
+ *     order, each block in k-j-i order (i fastest), interior cells only.
+ *     Conservative variables (rho, rho u, rho v[, rho w], rho E) unless an
+ *     entry point says primitive (rho, u, v[, w], p).
+ *   Nodes of a block: [coord][k][j][i] with (ni+1)(nj+1)(nk+1) points per
+ *     coordinate (nk+1 -> 1 in 2D), i fastest; concatenated over blocks in
+ *     the node-sized entry points.
+ *   Faces: 0..5 = imin, imax, jmin, jmax, kmin, kmax.  A face range lo/hi is a
+ *     half-open cell-index range along the face's tangential axes in
+ *     increasing axis order (i before j before k); in 2D only [0] is used.
+ *
+ * Calls are asynchronous on the stream given to cfd_create unless stated.
+ * Errors: every call returns a cfd_status; cfd_last_error() gives detail.
+ * Calls in the wrong order return CFD_ERR_STATE.  One context must not be
+ * used from two threads at once.
+ */
+#ifndef CFDHIP_H
+#define CFDHIP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cfd_ctx cfd_ctx;
+
+typedef enum {
+  CFD_OK = 0,
+  CFD_ERR_ARG = -1,         /* bad argument (null pointer, size, enum) */
+  CFD_ERR_STATE = -2,       /* call out of order (e.g. before finalize/bind) */
+  CFD_ERR_TOPOLOGY = -3,    /* connection or patch extents do not match / overlap */
+  CFD_ERR_GRID = -4,        /* non-positive cell volume or degenerate face */
+  CFD_ERR_HIP = -5,         /* HIP runtime error */
+  CFD_ERR_NONFINITE = -6,   /* non-finite or non-physical state detected */
+  CFD_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+} cfd_status;
+
+enum { CFD_LIM_NONE = 0, CFD_LIM_VANLEER = 1, CFD_LIM_VANALBADA = 2 };
+enum { CFD_BC_SLIP_WALL = 1, CFD_BC_SUP_INFLOW = 2, CFD_BC_EXTRAP_OUTFLOW = 3 };
+enum { CFD_DT_CFL = 0, CFD_DT_FIXED = 1 };
+/* execution modes for cfd_set_exec */
+enum { CFD_EXEC_BATCHED = 0, CFD_EXEC_PER_BLOCK = 1 };
+
+typedef struct {
+  int dim;              /* 2 or 3 */
+  double gamma;         /* ratio of specific heats (1.4) */
+  int limiter;          /* CFD_LIM_*; symmetric limiters only (van Leer, van Albada) or none */
+  double muscl_eps;     /* MUSCL epsilon of eq. (flux); 1 = second order */
+  double muscl_kappa;   /* MUSCL kappa of eq. (flux); face states do not depend on it
+                           for the symmetric limiters, the value is validated only */
+  double lim_eps[5];    /* van Albada regularisation per primitive variable (rho,u,v[,w],p) */
+  double efix;          /* Harten smoothing half-width as a fraction of the Roe sound speed; 0 = off */
+  int rk_stages;        /* M of the M-stage scheme, alpha_k = 1/(M-k+1); 1..8 */
+  int dt_mode;          /* CFD_DT_CFL: global CFL step from Q^n each step; CFD_DT_FIXED */
+  double cfl;           /* CFL number for CFD_DT_CFL */
+  double dt_fixed;      /* time step for CFD_DT_FIXED */
+} cfd_config;
+
+/* Version string of the library build. */
+const char* cfd_version(void);
+const char* cfd_status_string(cfd_status s);
+/* Last error message of a context (never NULL; "" if none). */
+const char* cfd_last_error(const cfd_ctx* ctx);
+
+/* Create a context on the current HIP device; hip_stream is a hipStream_t
+ * (NULL = the default stream) on which all later work is enqueued.
+ * Errors: CFD_ERR_ARG for an invalid config (dim, gamma <= 1, stages, cfl). */
+cfd_status cfd_create(const cfd_config* cfg, void* hip_stream, cfd_ctx** out);
+cfd_status cfd_destroy(cfd_ctx* ctx);
+
+/* Add a block of ni x nj (x nk) cells (nk = 1 in 2D; every extent >= 2).
+ * nodes_host: node coordinates as described above, copied by the call.
+ * Returns the block id (0, 1, ...) in *block_id.  Only before cfd_finalize. */
+cfd_status cfd_add_block(cfd_ctx* ctx, int ni, int nj, int nk, const double* nodes_host, int* block_id);
+
+/* Physical boundary patch on a face range of a block (Sec. 2 boundary types;
+ * the paper names the types but prints no formulas; these are the readings):
+ *   CFD_BC_SLIP_WALL       mirror ghosts, wall-face flux (0, p_w S, 0), p_w = 1.5 p0 - 0.5 p1
+ *   CFD_BC_SUP_INFLOW      both ghost layers = params_host[0..dim+1] (primitive)
+ *   CFD_BC_EXTRAP_OUTFLOW  both ghost layers = adjacent interior cell
+ * Returns a patch id in *patch_id (may be NULL).  Ranges may not overlap other
+ * patches or connections (checked at finalize: CFD_ERR_TOPOLOGY). */
+cfd_status cfd_set_bc(cfd_ctx* ctx, int block, int face, const int lo[2], const int hi[2],
+                      int bc_type, const double* params_host, int* patch_id);
+
+/* Connect face range A of block_a with face range B of block_b (a block may
+ * connect to itself: periodic).  Both sides' two ghost layers are filled from
+ * the other side's first two interior layers at every stage.  orient maps an
+ * offset (r1, r2) inside range A to the offset inside range B: (s1, s2) =
+ * (r2, r1) if bit 2 is set else (r1, r2); then s_m is reversed along B's m-th
+ * tangential axis if bit (m-1) is set.  Extents must agree under the map. */
+cfd_status cfd_connect(cfd_ctx* ctx, int block_a, int face_a, const int lo_a[2], const int hi_a[2],
+                       int block_b, int face_b, const int lo_b[2], const int hi_b[2], int orient);
+
+/* Validate the topology and plan all device tables and tiles.  Returns the
+ * number of workspace bytes the context needs in *workspace_bytes.
+ * Errors: CFD_ERR_STATE (no blocks), CFD_ERR_TOPOLOGY. */
+cfd_status cfd_finalize(cfd_ctx* ctx, size_t* workspace_bytes);
+
+/* Bind caller-allocated device memory (>= workspace_bytes, 256-byte aligned)
+ * as the context's workspace; uploads tables and nodes and computes the
+ * metrics on the device.  Synchronises the stream.
+ * Errors: CFD_ERR_ARG (size/alignment), CFD_ERR_GRID (non-positive volume). */
+cfd_status cfd_bind_workspace(cfd_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Replace the node coordinates of all blocks (device, concatenated node
+ * layout) and recompute the metrics.  Synchronises; CFD_ERR_GRID on a
+ * non-positive volume. */
+cfd_status cfd_set_nodes(cfd_ctx* ctx, const double* dev_nodes);
+/* Update the primitive parameters of an inflow patch (host array of dim+2). */
+cfd_status cfd_set_bc_params(cfd_ctx* ctx, int patch_id, const double* params_host);
+
+/* Set the solution from packed conservative (cfd_set_state) or primitive
+ * (cfd_set_state_primitive) variables; the CFL step of the new state is
+ * recomputed.  Synchronises; CFD_ERR_NONFINITE if any density or pressure is
+ * not positive and finite. */
+cfd_status cfd_set_state(cfd_ctx* ctx, const double* dev_Q);
+cfd_status cfd_set_state_primitive(cfd_ctx* ctx, const double* dev_q);
+/* Packed conservative copy of the current solution. */
+cfd_status cfd_get_state(cfd_ctx* ctx, double* dev_Q);
+
+/* Residual R(Q) of the current state, packed conservative layout, with
+ * dQ/dt = -R: ghost fill (connections, then physical patches), MUSCL face
+ * states, Roe flux on every face, wall-flux override, flux divergence / volume. */
+cfd_status cfd_residual(cfd_ctx* ctx, double* dev_R);
+
+/* Global CFL time step CFL * min(Omega / lambda) of the current state, or the
+ * fixed step, written to dev_dt[0]. */
+cfd_status cfd_time_step(cfd_ctx* ctx, double* dev_dt);
+
+/* Advance nsteps M-stage Runge-Kutta steps in place.  The time step of each
+ * step is computed on the device from the state at the start of the step
+ * (CFD_DT_CFL) or fixed.  If dev_dt_last is not NULL the step used last is
+ * written there. */
+cfd_status cfd_rk_step(cfd_ctx* ctx, int nsteps, double* dev_dt_last);
+
+/* Padded primitive arrays of all blocks after a ghost fill of the current
+ * state (connections, then physical patches): block after block, each
+ * [var][k+2][j+2][i+2] with extents (nk+4) (1 in 2D), (nj+4), (ni+4).
+ * Corner ghost cells are undefined.  For inspection and tests. */
+cfd_status cfd_padded_primitives(cfd_ctx* ctx, double* dev_out);
+/* Element count of the cfd_padded_primitives output. */
+cfd_status cfd_padded_size(cfd_ctx* ctx, size_t* count);
+
+/* Execution mode of rk_step/residual: CFD_EXEC_BATCHED launches every phase
+ * once for all blocks (tile list over every block, grid-stride loop);
+ * CFD_EXEC_PER_BLOCK launches each phase once per block.  use_graph != 0
+ * captures one Runge-Kutta step in a hipGraph (batched mode only). */
+cfd_status cfd_set_exec(cfd_ctx* ctx, int mode, int use_graph);
+
+/* Time every compiled tile shape of the stage kernel on the bound problem
+ * (reps launches each) and keep the fastest.  *chosen (may be NULL) receives
+ * the index of the chosen variant.  Synchronises. */
+cfd_status cfd_autotune(cfd_ctx* ctx, int reps, int* chosen);
+/* Select a tile-shape variant by index (0 .. cfd_query(CFD_Q_NVARIANTS)-1). */
+cfd_status cfd_set_variant(cfd_ctx* ctx, int variant);
+
+/* Kernel timing: while enabled, rk_step records HIP events around every
+ * stage-kernel launch on the context stream (graph capture is bypassed).
+ * cfd_kernel_time returns the summed stage-kernel time in ms and the launch
+ * count since the last enable; it synchronises. */
+cfd_status cfd_profile(cfd_ctx* ctx, int enable);
+cfd_status cfd_kernel_time(cfd_ctx* ctx, double* total_ms, long long* launches);
+
+enum {
+  CFD_Q_NBLOCKS = 0, CFD_Q_NCELLS = 1, CFD_Q_NVAR = 2, CFD_Q_NVARIANTS = 3, CFD_Q_VARIANT = 4,
+  CFD_Q_NTILES = 5, CFD_Q_NTRANSFERS = 6, CFD_Q_NPATCHES = 7, CFD_Q_NNODES = 8,
+  CFD_Q_EXCHANGE_DOUBLES = 9, CFD_Q_WORKSPACE_BYTES = 10, CFD_Q_TILE_X = 11, CFD_Q_TILE_Y = 12
+};
+/* Integer facts about a finalized context. */
+cfd_status cfd_query(cfd_ctx* ctx, int what, long long* value);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFDHIP_H */

@@ -1,0 +1,1008 @@
+// C ABI of the Euler hot-path library: topology planning, workspace layout,
+// launch sequencing (per-block or batched, optionally as a hipGraph), the
+// tile-shape autotuner and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cfdhip.h"
+#include "cfd_internal.h"
+#include "kernels.h"
+#include "stage_kernel.h"
+
+using namespace cfd;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+long long align_ll(long long x, long long a) { return (x + a - 1) / a * a; }
+
+struct HBlock {
+  int ni, nj, nk;
+  std::vector<double> nodes;
+};
+struct HPatch {
+  int block, face, lo[2], hi[2], kind;
+  double params[MAXV];
+  int param_index;
+};
+struct HConn {
+  int a, fa, loa[2], hia[2], b, fb, lob[2], hib[2], orient;
+};
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct cfd_ctx {
+  cfd_config cfg{};
+  int dim = 2, nvar = 4;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int device = 0;
+  std::string err;
+
+  std::vector<HBlock> hblocks;
+  std::vector<HPatch> hpatches;
+  std::vector<HConn> hconns;
+  bool finalized = false, bound = false, have_state = false, dt_valid = false;
+
+  // planned tables (host copies of what is uploaded)
+  std::vector<BlockDev> blocks;
+  std::vector<TransferDev> xfers;
+  std::vector<PatchDev> patches;
+  std::vector<ChunkDev> chunks1, chunks2;     // phase 1 (pack + patches) and 2 (unpack), block-sorted
+  std::vector<int> c1_begin, c2_begin;        // per-block chunk ranges (size nblocks + 1)
+  int nvariants = 0;
+  std::vector<std::vector<TileDev>> tiles_batched, tiles_block;  // per variant
+  std::vector<std::vector<int>> tile_begin;                      // per variant, per block (+1)
+  std::vector<long long> export_off;
+  long long ncells = 0, nnodes = 0, max_cells = 0, max_padded = 0, max_pos = 0, padded_total = 0;
+  long long state_doubles = 0, metric_doubles = 0, xbuf_doubles = 0;
+  int ninflow = 0;
+
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t off_stA = 0, off_stB = 0, off_stC = 0, off_metric = 0, off_nodes = 0, off_xbuf = 0, off_inflow = 0,
+         off_dt = 0, off_dtmin = 0, off_err = 0, off_blocks = 0, off_xfers = 0, off_patches = 0, off_chunks1 = 0,
+         off_chunks2 = 0, off_export = 0;
+  std::vector<size_t> off_tiles_batched, off_tiles_block;
+
+  // execution
+  int variant = 0;
+  int exec_mode = CFD_EXEC_BATCHED;
+  int use_graph = 1;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  bool graph_valid = false;
+
+  // timing
+  bool profiling = false;
+  std::vector<EventPair> ev_pool;
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  long long prof_launches = 0;
+
+  template <class T>
+  T* dptr(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+  double* stA() const { return dptr<double>(off_stA); }
+  double* stB() const { return dptr<double>(off_stB); }
+  double* stC() const { return dptr<double>(off_stC); }
+  double* metric() const { return dptr<double>(off_metric); }
+};
+
+namespace {
+
+cfd_status fail(cfd_ctx* c, cfd_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                        \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return fail(ctx, CFD_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int face_axis(int f) { return f >> 1; }
+
+void face_extent(const HBlock& b, int dim, int face, int ext[2]) {
+  int n[3] = {b.ni, b.nj, b.nk};
+  int axis = face_axis(face);
+  int m = 0;
+  ext[0] = ext[1] = 1;
+  for (int a = 0; a < dim; ++a)
+    if (a != axis) ext[m++] = n[a];
+}
+
+Gas make_gas(double gamma) {
+  Gas g;
+  g.gamma = gamma;
+  g.gm1 = gamma - 1.0;
+  g.igm1 = 1.0 / (gamma - 1.0);
+  g.g_gm1 = gamma / (gamma - 1.0);
+  return g;
+}
+
+int inverse_orient(int o) {
+  if (!(o & 4)) return o;
+  return 4 | ((o & 2) ? 1 : 0) | ((o & 1) ? 2 : 0);
+}
+
+// workgroup w runs on XCD w % 8; give each XCD a contiguous run of spatially
+// ordered tiles so halo re-reads of neighbouring tiles hit the same L2.
+std::vector<TileDev> xcd_order(const std::vector<TileDev>& spatial, size_t begin, size_t end) {
+  const size_t n = end - begin;
+  std::vector<TileDev> out(n);
+  const size_t q = n / 8, rem = n % 8;
+  for (size_t w = 0; w < n; ++w) {
+    const size_t x = w % 8, m = w / 8;
+    const size_t start = x * q + std::min(x, rem);
+    out[w] = spatial[begin + start + m];
+  }
+  return out;
+}
+
+cfd_status need(cfd_ctx* c, bool finalized, bool bound) {
+  if (!c) return CFD_ERR_ARG;
+  if (finalized && !c->finalized) return fail(c, CFD_ERR_STATE, "context is not finalized");
+  if (bound && !c->bound) return fail(c, CFD_ERR_STATE, "no workspace bound");
+  return CFD_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" const char* cfd_version(void) { return "cfdhip 0.1 (gfx950, fp64)"; }
+
+extern "C" const char* cfd_status_string(cfd_status s) {
+  switch (s) {
+    case CFD_OK: return "ok";
+    case CFD_ERR_ARG: return "invalid argument";
+    case CFD_ERR_STATE: return "call out of order";
+    case CFD_ERR_TOPOLOGY: return "invalid topology";
+    case CFD_ERR_GRID: return "invalid grid";
+    case CFD_ERR_HIP: return "HIP runtime error";
+    case CFD_ERR_NONFINITE: return "non-finite or non-physical state";
+    case CFD_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* cfd_last_error(const cfd_ctx* c) { return c ? c->err.c_str() : ""; }
+
+extern "C" cfd_status cfd_create(const cfd_config* cfg, void* stream, cfd_ctx** out) {
+  if (!cfg || !out) return CFD_ERR_ARG;
+  *out = nullptr;
+  if (cfg->dim != 2 && cfg->dim != 3) return CFD_ERR_ARG;
+  if (!(cfg->gamma > 1.0)) return CFD_ERR_ARG;
+  if (cfg->limiter < CFD_LIM_NONE || cfg->limiter > CFD_LIM_VANALBADA) return CFD_ERR_ARG;
+  if (cfg->rk_stages < 1 || cfg->rk_stages > 8) return CFD_ERR_ARG;
+  if (cfg->dt_mode == CFD_DT_CFL && !(cfg->cfl > 0.0)) return CFD_ERR_ARG;
+  if (cfg->dt_mode == CFD_DT_FIXED && !(cfg->dt_fixed > 0.0)) return CFD_ERR_ARG;
+  if (cfg->dt_mode != CFD_DT_CFL && cfg->dt_mode != CFD_DT_FIXED) return CFD_ERR_ARG;
+  if (!(cfg->efix >= 0.0) || !(cfg->muscl_eps >= 0.0)) return CFD_ERR_ARG;
+  for (int v = 0; v < MAXV; ++v)
+    if (!(cfg->lim_eps[v] >= 0.0)) return CFD_ERR_ARG;
+  cfd_ctx* c = new cfd_ctx();
+  c->cfg = *cfg;
+  c->dim = cfg->dim;
+  c->nvar = cfg->dim + 2;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  // Without a usable device the context still plans (add/set/connect/finalize);
+  // binding a workspace then fails with CFD_ERR_HIP.
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+  int n = 0;
+  stage_variants(c->dim, &n);
+  c->nvariants = n;
+  *out = c;
+  return CFD_OK;
+}
+
+static void release_graph(cfd_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_valid = false;
+}
+
+extern "C" cfd_status cfd_destroy(cfd_ctx* c) {
+  if (!c) return CFD_ERR_ARG;
+  release_graph(c);
+  for (auto& e : c->ev_pool) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_add_block(cfd_ctx* c, int ni, int nj, int nk, const double* nodes, int* id) {
+  if (!c || !nodes) return CFD_ERR_ARG;
+  if (c->finalized) return fail(c, CFD_ERR_STATE, "add_block after finalize");
+  if (c->dim == 2 && nk != 1) return fail(c, CFD_ERR_ARG, "2D blocks need nk = 1");
+  if (ni < 2 || nj < 2 || (c->dim == 3 && nk < 2)) return fail(c, CFD_ERR_ARG, "block extents must be >= 2");
+  if ((long long)ni * nj * nk > (1LL << 31)) return fail(c, CFD_ERR_ARG, "block too large");
+  HBlock b{ni, nj, nk, {}};
+  const size_t nn = (size_t)(ni + 1) * (nj + 1) * (c->dim == 3 ? nk + 1 : 1);
+  b.nodes.assign(nodes, nodes + nn * c->dim);
+  c->hblocks.push_back(std::move(b));
+  if (id) *id = (int)c->hblocks.size() - 1;
+  return CFD_OK;
+}
+
+static cfd_status check_range(cfd_ctx* c, int block, int face, const int lo[2], const int hi[2]) {
+  if (block < 0 || block >= (int)c->hblocks.size()) return fail(c, CFD_ERR_ARG, "bad block id %d", block);
+  if (face < 0 || face >= 2 * c->dim) return fail(c, CFD_ERR_ARG, "bad face %d", face);
+  int ext[2];
+  face_extent(c->hblocks[block], c->dim, face, ext);
+  for (int t = 0; t < c->dim - 1; ++t)
+    if (lo[t] < 0 || hi[t] > ext[t] || lo[t] >= hi[t])
+      return fail(c, CFD_ERR_ARG, "range [%d,%d) outside face extent %d", lo[t], hi[t], ext[t]);
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_set_bc(cfd_ctx* c, int block, int face, const int lo[2], const int hi[2], int kind,
+                                 const double* params, int* patch_id) {
+  if (!c || !lo || !hi) return CFD_ERR_ARG;
+  if (c->finalized) return fail(c, CFD_ERR_STATE, "set_bc after finalize");
+  cfd_status s = check_range(c, block, face, lo, hi);
+  if (s != CFD_OK) return s;
+  if (kind != CFD_BC_SLIP_WALL && kind != CFD_BC_SUP_INFLOW && kind != CFD_BC_EXTRAP_OUTFLOW)
+    return fail(c, CFD_ERR_ARG, "bad boundary kind %d", kind);
+  HPatch p{};
+  p.block = block;
+  p.face = face;
+  p.kind = kind;
+  p.param_index = -1;
+  for (int t = 0; t < 2; ++t) {
+    p.lo[t] = t < c->dim - 1 ? lo[t] : 0;
+    p.hi[t] = t < c->dim - 1 ? hi[t] : 1;
+  }
+  if (kind == CFD_BC_SUP_INFLOW) {
+    if (!params) return fail(c, CFD_ERR_ARG, "inflow patch needs parameters");
+    for (int v = 0; v < c->nvar; ++v) p.params[v] = params[v];
+    if (!(p.params[0] > 0.0) || !(p.params[c->nvar - 1] > 0.0))
+      return fail(c, CFD_ERR_NONFINITE, "inflow density and pressure must be positive");
+    p.param_index = c->ninflow++;
+  }
+  c->hpatches.push_back(p);
+  if (patch_id) *patch_id = (int)c->hpatches.size() - 1;
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_connect(cfd_ctx* c, int a, int fa, const int loa[2], const int hia[2], int b, int fb,
+                                  const int lob[2], const int hib[2], int orient) {
+  if (!c || !loa || !hia || !lob || !hib) return CFD_ERR_ARG;
+  if (c->finalized) return fail(c, CFD_ERR_STATE, "connect after finalize");
+  cfd_status s = check_range(c, a, fa, loa, hia);
+  if (s != CFD_OK) return s;
+  s = check_range(c, b, fb, lob, hib);
+  if (s != CFD_OK) return s;
+  if (orient < 0 || orient > 7 || (c->dim == 2 && orient > 1)) return fail(c, CFD_ERR_ARG, "bad orient %d", orient);
+  HConn h{};
+  h.a = a;
+  h.fa = fa;
+  h.b = b;
+  h.fb = fb;
+  h.orient = orient;
+  for (int t = 0; t < 2; ++t) {
+    h.loa[t] = t < c->dim - 1 ? loa[t] : 0;
+    h.hia[t] = t < c->dim - 1 ? hia[t] : 1;
+    h.lob[t] = t < c->dim - 1 ? lob[t] : 0;
+    h.hib[t] = t < c->dim - 1 ? hib[t] : 1;
+  }
+  int la0 = h.hia[0] - h.loa[0], la1 = h.hia[1] - h.loa[1];
+  int lb0 = h.hib[0] - h.lob[0], lb1 = h.hib[1] - h.lob[1];
+  bool ok = (orient & 4) ? (la0 == lb1 && la1 == lb0) : (la0 == lb0 && la1 == lb1);
+  if (!ok) return fail(c, CFD_ERR_TOPOLOGY, "connection extents do not match under orient %d", orient);
+  int na = face_axis(fa) == 0 ? c->hblocks[a].ni : (face_axis(fa) == 1 ? c->hblocks[a].nj : c->hblocks[a].nk);
+  int nb = face_axis(fb) == 0 ? c->hblocks[b].ni : (face_axis(fb) == 1 ? c->hblocks[b].nj : c->hblocks[b].nk);
+  if (na < NG || nb < NG) return fail(c, CFD_ERR_TOPOLOGY, "connected blocks need at least %d layers", NG);
+  if (a == b && fa == fb) {
+    // a face connected to itself must map every cell to a different one or it would copy onto itself
+    bool overlap = !(h.hia[0] <= h.lob[0] || h.hib[0] <= h.loa[0]) && !(h.hia[1] <= h.lob[1] || h.hib[1] <= h.loa[1]);
+    if (overlap && orient == 0) return fail(c, CFD_ERR_TOPOLOGY, "face connected onto itself");
+  }
+  c->hconns.push_back(h);
+  return CFD_OK;
+}
+
+// ---------------------------------------------------------------------------
+
+extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
+  if (!c) return CFD_ERR_ARG;
+  if (c->finalized) return fail(c, CFD_ERR_STATE, "already finalized");
+  if (c->hblocks.empty()) return fail(c, CFD_ERR_STATE, "no blocks");
+  const int dim = c->dim, nv = c->nvar;
+  const int nb = (int)c->hblocks.size();
+
+  // --- boundary coverage: every boundary face cell exactly once -----------
+  for (int b = 0; b < nb; ++b) {
+    for (int f = 0; f < 2 * dim; ++f) {
+      int ext[2];
+      face_extent(c->hblocks[b], dim, f, ext);
+      std::vector<unsigned char> cov((size_t)ext[0] * ext[1], 0);
+      auto mark = [&](const int lo[2], const int hi[2]) -> bool {
+        for (int t2 = lo[1]; t2 < hi[1]; ++t2)
+          for (int t1 = lo[0]; t1 < hi[0]; ++t1)
+            if (cov[(size_t)t2 * ext[0] + t1]++) return false;
+        return true;
+      };
+      for (auto& p : c->hpatches)
+        if (p.block == b && p.face == f && !mark(p.lo, p.hi))
+          return fail(c, CFD_ERR_TOPOLOGY, "block %d face %d: overlapping boundary definitions", b, f);
+      for (auto& h : c->hconns) {
+        if (h.a == b && h.fa == f && !mark(h.loa, h.hia))
+          return fail(c, CFD_ERR_TOPOLOGY, "block %d face %d: overlapping boundary definitions", b, f);
+        if (h.b == b && h.fb == f && !mark(h.lob, h.hib))
+          return fail(c, CFD_ERR_TOPOLOGY, "block %d face %d: overlapping boundary definitions", b, f);
+      }
+      for (auto v : cov)
+        if (v == 0) return fail(c, CFD_ERR_TOPOLOGY, "block %d face %d has cells without a boundary condition", b, f);
+    }
+  }
+
+  // --- block layout ---------------------------------------------------------
+  c->blocks.resize(nb);
+  long long cursor = 0, mcursor = 0, packed = 0, node0 = 0;
+  const int nmet = dim * dim + 1;
+  c->max_cells = c->max_padded = c->max_pos = 0;
+  c->padded_total = 0;
+  c->export_off.assign(nb, 0);
+  for (int b = 0; b < nb; ++b) {
+    const HBlock& h = c->hblocks[b];
+    BlockDev& B = c->blocks[b];
+    B.ni = h.ni;
+    B.nj = h.nj;
+    B.nk = h.nk;
+    B.pi = (int)align_ll(h.ni + 4, 16);
+    B.pj = h.nj + 4;
+    const long long pk = dim == 3 ? h.nk + 4 : 1;
+    const long long padded = (long long)B.pi * B.pj * pk;
+    B.vstride = align_ll(padded, 16);
+    const long long K = ((dim == 3 ? 2LL * B.pj : 0LL) + 2) * B.pi + 2;  // origin - array base
+    // array base at cursor + 14 puts the origin (K = 2 mod 16) on a 16-double boundary
+    B.origin = cursor + 14 + K;
+    cursor = align_ll(cursor + 14 + (nv - 1) * B.vstride + padded, 16);
+    B.morigin = mcursor + 14 + K;
+    mcursor = align_ll(mcursor + 14 + (nmet - 1) * B.vstride + padded, 16);
+    B.packed = packed;
+    const long long ncell = (long long)h.ni * h.nj * h.nk;
+    packed += ncell;
+    B.node0 = node0;
+    const long long nnode = (long long)(h.ni + 1) * (h.nj + 1) * (dim == 3 ? h.nk + 1 : 1);
+    node0 += nnode;
+    B.wall_mask = 0;
+    for (auto& p : c->hpatches)
+      if (p.block == b && p.kind == CFD_BC_SLIP_WALL) B.wall_mask |= 1 << p.face;
+    c->max_cells = std::max(c->max_cells, ncell);
+    const long long pe = (long long)(h.ni + 4) * (h.nj + 4) * (dim == 3 ? h.nk + 4 : 1);
+    c->max_padded = std::max(c->max_padded, pe);
+    c->export_off[b] = c->padded_total;
+    c->padded_total += pe * nv;
+    c->max_pos = std::max(c->max_pos, (long long)(h.ni + 1) * (h.nj + 1) * (dim == 3 ? h.nk + 1 : 1));
+  }
+  for (auto& B : c->blocks) {
+    B.ncell_total = packed;
+    B.nnode_total = node0;
+  }
+  c->ncells = packed;
+  c->nnodes = node0;
+  c->state_doubles = cursor;
+  c->metric_doubles = mcursor;
+
+  // --- transfers, patches and ghost-fill chunks ------------------------------
+  c->xfers.clear();
+  long long xoff = 0;
+  for (auto& h : c->hconns) {
+    for (int dir = 0; dir < 2; ++dir) {
+      TransferDev x{};
+      const bool ab = dir == 0;  // receiver a, donor b
+      x.rblock = ab ? h.a : h.b;
+      x.rface = ab ? h.fa : h.fb;
+      x.dblock = ab ? h.b : h.a;
+      x.dface = ab ? h.fb : h.fa;
+      const int* rlo = ab ? h.loa : h.lob;
+      const int* rhi = ab ? h.hia : h.hib;
+      const int* dlo = ab ? h.lob : h.loa;
+      const int* dhi = ab ? h.hib : h.hia;
+      x.rlo0 = rlo[0];
+      x.rlo1 = rlo[1];
+      x.len0 = rhi[0] - rlo[0];
+      x.len1 = rhi[1] - rlo[1];
+      x.dlo0 = dlo[0];
+      x.dlo1 = dlo[1];
+      x.dlen0 = dhi[0] - dlo[0];
+      x.dlen1 = dhi[1] - dlo[1];
+      x.orient = ab ? h.orient : inverse_orient(h.orient);
+      x.buf = xoff;
+      xoff += (long long)nv * NG * x.len0 * x.len1;
+      c->xfers.push_back(x);
+    }
+  }
+  c->xbuf_doubles = std::max(xoff, 16LL);
+  c->patches.clear();
+  for (auto& p : c->hpatches) {
+    PatchDev d{};
+    d.block = p.block;
+    d.face = p.face;
+    d.kind = p.kind;
+    d.param = p.param_index;
+    d.lo0 = p.lo[0];
+    d.lo1 = p.lo[1];
+    d.len0 = p.hi[0] - p.lo[0];
+    d.len1 = p.hi[1] - p.lo[1];
+    c->patches.push_back(d);
+  }
+  // phase 1 chunks sorted by owning block (pack: donor; patch: its block); phase 2 by receiver
+  c->chunks1.clear();
+  c->chunks2.clear();
+  c->c1_begin.assign(nb + 1, 0);
+  c->c2_begin.assign(nb + 1, 0);
+  auto add_chunks = [](std::vector<ChunkDev>& v, int kind, int item, int count) {
+    for (int s = 0; s < count; s += CHUNK) v.push_back(ChunkDev{kind, item, s, std::min(CHUNK, count - s)});
+  };
+  for (int b = 0; b < nb; ++b) {
+    c->c1_begin[b] = (int)c->chunks1.size();
+    for (size_t x = 0; x < c->xfers.size(); ++x)
+      if (c->xfers[x].dblock == b) add_chunks(c->chunks1, 0, (int)x, NG * c->xfers[x].len0 * c->xfers[x].len1);
+    for (size_t p = 0; p < c->patches.size(); ++p)
+      if (c->patches[p].block == b) add_chunks(c->chunks1, 1, (int)p, NG * c->patches[p].len0 * c->patches[p].len1);
+    c->c2_begin[b] = (int)c->chunks2.size();
+    for (size_t x = 0; x < c->xfers.size(); ++x)
+      if (c->xfers[x].rblock == b) add_chunks(c->chunks2, 2, (int)x, NG * c->xfers[x].len0 * c->xfers[x].len1);
+  }
+  c->c1_begin[nb] = (int)c->chunks1.size();
+  c->c2_begin[nb] = (int)c->chunks2.size();
+
+  // --- tiles per variant -------------------------------------------------------
+  int nvar_t = 0;
+  const StageVariant* vars = stage_variants(dim, &nvar_t);
+  c->nvariants = nvar_t;
+  c->tiles_batched.assign(nvar_t, {});
+  c->tiles_block.assign(nvar_t, {});
+  c->tile_begin.assign(nvar_t, std::vector<int>(nb + 1, 0));
+  for (int v = 0; v < nvar_t; ++v) {
+    std::vector<TileDev> spatial;
+    for (int b = 0; b < nb; ++b) {
+      c->tile_begin[v][b] = (int)spatial.size();
+      const BlockDev& B = c->blocks[b];
+      const int kc = dim == 3 ? vars[v].kc : 1;
+      const int nk = dim == 3 ? B.nk : 1;
+      for (int k0 = 0; k0 < nk; k0 += kc)
+        for (int j0 = 0; j0 < B.nj; j0 += vars[v].ty)
+          for (int i0 = 0; i0 < B.ni; i0 += vars[v].tx) spatial.push_back(TileDev{b, i0, j0, k0});
+    }
+    c->tile_begin[v][nb] = (int)spatial.size();
+    c->tiles_batched[v] = xcd_order(spatial, 0, spatial.size());
+    std::vector<TileDev> per;
+    for (int b = 0; b < nb; ++b) {
+      auto part = xcd_order(spatial, c->tile_begin[v][b], c->tile_begin[v][b + 1]);
+      per.insert(per.end(), part.begin(), part.end());
+    }
+    c->tiles_block[v] = per;
+  }
+
+  // --- workspace layout ---------------------------------------------------------
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1), ALIGN);
+    return o;
+  };
+  c->off_stA = take(c->state_doubles * 8);
+  c->off_stB = take(c->state_doubles * 8);
+  c->off_stC = take(c->state_doubles * 8);
+  c->off_metric = take(c->metric_doubles * 8);
+  c->off_nodes = take((size_t)c->nnodes * dim * 8);
+  c->off_xbuf = take(c->xbuf_doubles * 8);
+  c->off_inflow = take((size_t)std::max(c->ninflow, 1) * MAXV * 8);
+  c->off_dt = take(2 * 8);
+  c->off_dtmin = take(8);
+  c->off_err = take(4);
+  c->off_blocks = take(c->blocks.size() * sizeof(BlockDev));
+  c->off_xfers = take(c->xfers.size() * sizeof(TransferDev));
+  c->off_patches = take(c->patches.size() * sizeof(PatchDev));
+  c->off_chunks1 = take(c->chunks1.size() * sizeof(ChunkDev));
+  c->off_chunks2 = take(c->chunks2.size() * sizeof(ChunkDev));
+  c->off_export = take(c->export_off.size() * sizeof(long long));
+  c->off_tiles_batched.assign(nvar_t, 0);
+  c->off_tiles_block.assign(nvar_t, 0);
+  for (int v = 0; v < nvar_t; ++v) {
+    c->off_tiles_batched[v] = take(c->tiles_batched[v].size() * sizeof(TileDev));
+    c->off_tiles_block[v] = take(c->tiles_block[v].size() * sizeof(TileDev));
+  }
+  c->ws_bytes = off;
+  c->finalized = true;
+  if (ws_bytes) *ws_bytes = off;
+  return CFD_OK;
+}
+
+// ---------------------------------------------------------------------------
+
+static cfd_status recompute_metrics(cfd_ctx* c) {
+  HIP_TRY(c, hipMemsetAsync(c->dptr<int>(c->off_err), 0, sizeof(int), c->stream));
+  MetricArgs m{c->dptr<BlockDev>(c->off_blocks), c->dptr<double>(c->off_nodes), c->metric(), c->dptr<int>(c->off_err)};
+  HIP_TRY(c, launch_metrics(c->dim, m, c->max_pos, (int)c->blocks.size(), c->stream));
+  int err = 0;
+  HIP_TRY(c, hipMemcpyAsync(&err, c->dptr<int>(c->off_err), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (err) return fail(c, CFD_ERR_GRID, "grid has a non-positive or non-finite cell volume");
+  c->dt_valid = false;
+  return CFD_OK;
+}
+
+template <class T>
+static cfd_status upload(cfd_ctx* c, size_t off, const std::vector<T>& v) {
+  if (v.empty()) return CFD_OK;
+  HIP_TRY(c, hipMemcpyAsync(c->ws + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_bind_workspace(cfd_ctx* c, void* ptr, size_t bytes) {
+  cfd_status s = need(c, true, false);
+  if (s != CFD_OK) return s;
+  if (c->device < 0) return fail(c, CFD_ERR_HIP, "no HIP device was available when the context was created");
+  if (!ptr || bytes < c->ws_bytes) return fail(c, CFD_ERR_ARG, "workspace too small (%zu < %zu)", bytes, c->ws_bytes);
+  if (reinterpret_cast<uintptr_t>(ptr) % ALIGN) return fail(c, CFD_ERR_ARG, "workspace must be %zu-byte aligned", ALIGN);
+  release_graph(c);
+  c->ws = static_cast<char*>(ptr);
+  c->bound = true;
+  // the state buffers start zeroed so unused padding never holds NaN patterns
+  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_stA, 0, c->off_nodes - c->off_stA, c->stream));
+  // tables
+  if ((s = upload(c, c->off_blocks, c->blocks)) != CFD_OK) return s;
+  if ((s = upload(c, c->off_xfers, c->xfers)) != CFD_OK) return s;
+  if ((s = upload(c, c->off_patches, c->patches)) != CFD_OK) return s;
+  if ((s = upload(c, c->off_chunks1, c->chunks1)) != CFD_OK) return s;
+  if ((s = upload(c, c->off_chunks2, c->chunks2)) != CFD_OK) return s;
+  if ((s = upload(c, c->off_export, c->export_off)) != CFD_OK) return s;
+  for (int v = 0; v < c->nvariants; ++v) {
+    if ((s = upload(c, c->off_tiles_batched[v], c->tiles_batched[v])) != CFD_OK) return s;
+    if ((s = upload(c, c->off_tiles_block[v], c->tiles_block[v])) != CFD_OK) return s;
+  }
+  // nodes: [coord][concatenated nodes]
+  std::vector<double> nodes((size_t)c->nnodes * c->dim);
+  for (size_t b = 0; b < c->hblocks.size(); ++b) {
+    const HBlock& h = c->hblocks[b];
+    const size_t nn = h.nodes.size() / c->dim;
+    for (int cc = 0; cc < c->dim; ++cc)
+      std::memcpy(&nodes[cc * c->nnodes + c->blocks[b].node0], &h.nodes[cc * nn], nn * 8);
+  }
+  if ((s = upload(c, c->off_nodes, nodes)) != CFD_OK) return s;
+  std::vector<double> inflow((size_t)std::max(c->ninflow, 1) * MAXV, 0.0);
+  for (auto& p : c->hpatches)
+    if (p.param_index >= 0)
+      for (int v = 0; v < c->nvar; ++v) inflow[(size_t)p.param_index * MAXV + v] = p.params[v];
+  if ((s = upload(c, c->off_inflow, inflow)) != CFD_OK) return s;
+  std::vector<double> dt = {c->cfg.dt_mode == CFD_DT_FIXED ? c->cfg.dt_fixed : 0.0, 0.0};
+  if ((s = upload(c, c->off_dt, dt)) != CFD_OK) return s;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return recompute_metrics(c);
+}
+
+extern "C" cfd_status cfd_set_nodes(cfd_ctx* c, const double* dev_nodes) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!dev_nodes) return CFD_ERR_ARG;
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_nodes, dev_nodes, (size_t)c->nnodes * c->dim * 8,
+                            hipMemcpyDeviceToDevice, c->stream));
+  return recompute_metrics(c);
+}
+
+extern "C" cfd_status cfd_set_bc_params(cfd_ctx* c, int patch_id, const double* params) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (patch_id < 0 || patch_id >= (int)c->hpatches.size() || !params) return CFD_ERR_ARG;
+  HPatch& p = c->hpatches[patch_id];
+  if (p.kind != CFD_BC_SUP_INFLOW) return fail(c, CFD_ERR_ARG, "patch %d is not an inflow patch", patch_id);
+  if (!(params[0] > 0.0) || !(params[c->nvar - 1] > 0.0))
+    return fail(c, CFD_ERR_NONFINITE, "inflow density and pressure must be positive");
+  for (int v = 0; v < c->nvar; ++v) p.params[v] = params[v];
+  double tmp[MAXV] = {0, 0, 0, 0, 0};
+  for (int v = 0; v < c->nvar; ++v) tmp[v] = params[v];
+  HIP_TRY(c, hipMemcpyAsync(c->dptr<double>(c->off_inflow) + (size_t)p.param_index * MAXV, tmp, sizeof tmp,
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return CFD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+
+static CellArgs cell_args(cfd_ctx* c) {
+  CellArgs a{};
+  a.blocks = c->dptr<BlockDev>(c->off_blocks);
+  a.metric = c->metric();
+  a.offsets = c->dptr<long long>(c->off_export);
+  a.dtmin = c->dptr<unsigned long long>(c->off_dtmin);
+  a.err = c->dptr<int>(c->off_err);
+  a.gas = make_gas(c->cfg.gamma);
+  return a;
+}
+
+static GhostArgs ghost_args(cfd_ctx* c, double* q) {
+  GhostArgs g{};
+  g.blocks = c->dptr<BlockDev>(c->off_blocks);
+  g.xfers = c->dptr<TransferDev>(c->off_xfers);
+  g.patches = c->dptr<PatchDev>(c->off_patches);
+  g.q = q;
+  g.buf = c->dptr<double>(c->off_xbuf);
+  g.inflow = c->dptr<double>(c->off_inflow);
+  g.metric = c->metric();
+  return g;
+}
+
+static StageArgs stage_args(cfd_ctx* c) {
+  StageArgs a{};
+  a.blocks = c->dptr<BlockDev>(c->off_blocks);
+  a.patches = c->dptr<PatchDev>(c->off_patches);
+  a.npatches = (int)c->patches.size();
+  a.metric = c->metric();
+  a.dt = c->dptr<double>(c->off_dt);
+  a.gas = make_gas(c->cfg.gamma);
+  a.half_eps = 0.5 * c->cfg.muscl_eps;
+  a.kappa = c->cfg.muscl_kappa;
+  a.efix = c->cfg.efix;
+  for (int v = 0; v < MAXV; ++v) a.e2[v] = c->cfg.lim_eps[v] * c->cfg.lim_eps[v];
+  return a;
+}
+
+// Fill every ghost layer of state buffer q: pack + physical patches, then unpack.
+static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s) {
+  GhostArgs g = ghost_args(c, q);
+  const int nb = (int)c->blocks.size();
+  if (c->exec_mode == CFD_EXEC_PER_BLOCK) {
+    g.chunks = c->dptr<ChunkDev>(c->off_chunks1);
+    for (int b = 0; b < nb; ++b) {
+      g.chunk_begin = c->c1_begin[b];
+      HIP_TRY(c, launch_ghost(c->dim, g, c->c1_begin[b + 1] - c->c1_begin[b], s));
+    }
+    g.chunks = c->dptr<ChunkDev>(c->off_chunks2);
+    for (int b = 0; b < nb; ++b) {
+      g.chunk_begin = c->c2_begin[b];
+      HIP_TRY(c, launch_ghost(c->dim, g, c->c2_begin[b + 1] - c->c2_begin[b], s));
+    }
+  } else {
+    g.chunks = c->dptr<ChunkDev>(c->off_chunks1);
+    g.chunk_begin = 0;
+    HIP_TRY(c, launch_ghost(c->dim, g, (int)c->chunks1.size(), s));
+    g.chunks = c->dptr<ChunkDev>(c->off_chunks2);
+    HIP_TRY(c, launch_ghost(c->dim, g, (int)c->chunks2.size(), s));
+  }
+  return CFD_OK;
+}
+
+static EventPair& next_event(cfd_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    EventPair e{};
+    (void)hipEventCreate(&e.a);
+    (void)hipEventCreate(&e.b);
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool timed) {
+  const int v = c->variant;
+  const int nb = (int)c->blocks.size();
+  EventPair* ev = nullptr;
+  if (timed) {
+    ev = &next_event(c);
+    HIP_TRY(c, hipEventRecord(ev->a, s));
+  }
+  if (c->exec_mode == CFD_EXEC_PER_BLOCK) {
+    a.tiles = c->dptr<TileDev>(c->off_tiles_block[v]);
+    for (int b = 0; b < nb; ++b) {
+      a.tile_begin = c->tile_begin[v][b];
+      a.tile_end = c->tile_begin[v][b + 1];
+      HIP_TRY(c, launch_stage(c->dim, c->cfg.limiter, v, a, a.tile_end - a.tile_begin, s));
+    }
+  } else {
+    a.tiles = c->dptr<TileDev>(c->off_tiles_batched[v]);
+    a.tile_begin = 0;
+    a.tile_end = (int)c->tiles_batched[v].size();
+    HIP_TRY(c, launch_stage(c->dim, c->cfg.limiter, v, a, a.tile_end, s));
+  }
+  if (timed) {
+    HIP_TRY(c, hipEventRecord(ev->b, s));
+    c->prof_launches += 1;
+  }
+  return CFD_OK;
+}
+
+// Enqueue one full Runge-Kutta step on stream s.
+static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
+  const bool cfl = c->cfg.dt_mode == CFD_DT_CFL;
+  if (cfl)
+    HIP_TRY(c, launch_dt_promote(c->dptr<double>(c->off_dt), c->dptr<unsigned long long>(c->off_dtmin), c->cfg.cfl, 1,
+                                 nullptr, s));
+  const int M = c->cfg.rk_stages;
+  double* A = c->stA();
+  double* Bf = c->stB();
+  double* Cf = c->stC();
+  double* in = A;
+  for (int k = 1; k <= M; ++k) {
+    double* out = (k == M) ? A : ((k % 2) ? Bf : Cf);
+    cfd_status st = fill_ghosts(c, in, s);
+    if (st != CFD_OK) return st;
+    StageArgs a = stage_args(c);
+    a.qin = in;
+    a.q0 = A;
+    a.qout = out;
+    a.mode = MODE_STAGE;
+    a.alpha = 1.0 / (double)(M - k + 1);
+    a.dtmin = (k == M && cfl) ? c->dptr<unsigned long long>(c->off_dtmin) : nullptr;
+    st = launch_stage_all(c, a, s, timed);
+    if (st != CFD_OK) return st;
+    in = out;
+  }
+  return CFD_OK;
+}
+
+static cfd_status ensure_dt(cfd_ctx* c) {
+  if (c->cfg.dt_mode != CFD_DT_CFL || c->dt_valid) return CFD_OK;
+  HIP_TRY(c, launch_set_u64(c->dptr<unsigned long long>(c->off_dtmin), 0x7ff0000000000000ULL, c->stream));
+  CellArgs a = cell_args(c);
+  a.src = c->stA();
+  HIP_TRY(c, launch_cell_dt(c->dim, a, c->max_cells, (int)c->blocks.size(), c->stream));
+  c->dt_valid = true;
+  return CFD_OK;
+}
+
+static cfd_status build_graph(cfd_ctx* c) {
+  release_graph(c);
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  cfd_status st = enqueue_step(c, c->cap_stream, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  if (st != CFD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(c, CFD_ERR_HIP, "stream capture: %s", hipGetErrorString(e));
+  c->graph = g;
+  HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+  c->graph_valid = true;
+  return CFD_OK;
+}
+
+// ---------------------------------------------------------------------------
+
+static cfd_status set_state_impl(cfd_ctx* c, const double* src, int primitive) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!src) return CFD_ERR_ARG;
+  HIP_TRY(c, hipMemsetAsync(c->dptr<int>(c->off_err), 0, sizeof(int), c->stream));
+  CellArgs a = cell_args(c);
+  a.src = src;
+  a.dst = c->stA();
+  a.flag_primitive = primitive;
+  HIP_TRY(c, launch_set_state(c->dim, a, c->max_cells, (int)c->blocks.size(), c->stream));
+  int err = 0;
+  HIP_TRY(c, hipMemcpyAsync(&err, c->dptr<int>(c->off_err), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (err) return fail(c, CFD_ERR_NONFINITE, "state has a non-positive or non-finite density or pressure");
+  c->have_state = true;
+  c->dt_valid = false;
+  return ensure_dt(c);
+}
+
+extern "C" cfd_status cfd_set_state(cfd_ctx* c, const double* dev_Q) { return set_state_impl(c, dev_Q, 0); }
+extern "C" cfd_status cfd_set_state_primitive(cfd_ctx* c, const double* dev_q) { return set_state_impl(c, dev_q, 1); }
+
+extern "C" cfd_status cfd_get_state(cfd_ctx* c, double* dev_Q) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!dev_Q) return CFD_ERR_ARG;
+  CellArgs a = cell_args(c);
+  a.src = c->stA();
+  a.dst = dev_Q;
+  HIP_TRY(c, launch_get_state(c->dim, a, c->max_cells, (int)c->blocks.size(), c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_residual(cfd_ctx* c, double* dev_R) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!dev_R) return CFD_ERR_ARG;
+  if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
+  s = fill_ghosts(c, c->stA(), c->stream);
+  if (s != CFD_OK) return s;
+  StageArgs a = stage_args(c);
+  a.qin = c->stA();
+  a.q0 = c->stA();
+  a.qout = nullptr;
+  a.Rout = dev_R;
+  a.mode = MODE_RESIDUAL;
+  return launch_stage_all(c, a, c->stream, false);
+}
+
+extern "C" cfd_status cfd_time_step(cfd_ctx* c, double* dev_dt) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!dev_dt) return CFD_ERR_ARG;
+  if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
+  if (c->cfg.dt_mode == CFD_DT_FIXED) {
+    HIP_TRY(c, launch_copy_dt(c->dptr<double>(c->off_dt), dev_dt, c->stream));
+    return CFD_OK;
+  }
+  if ((s = ensure_dt(c)) != CFD_OK) return s;
+  HIP_TRY(c, launch_dt_promote(c->dptr<double>(c->off_dt), c->dptr<unsigned long long>(c->off_dtmin), c->cfg.cfl, 0,
+                               dev_dt, c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_rk_step(cfd_ctx* c, int nsteps, double* dev_dt_last) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (nsteps < 0) return CFD_ERR_ARG;
+  if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
+  if ((s = ensure_dt(c)) != CFD_OK) return s;
+  const bool graph = c->use_graph && c->exec_mode == CFD_EXEC_BATCHED && !c->profiling;
+  if (graph && !c->graph_valid && nsteps > 0)
+    if ((s = build_graph(c)) != CFD_OK) return s;
+  for (int n = 0; n < nsteps; ++n) {
+    if (graph) {
+      HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+    } else if ((s = enqueue_step(c, c->stream, c->profiling)) != CFD_OK) {
+      return s;
+    }
+  }
+  if (dev_dt_last) HIP_TRY(c, launch_copy_dt(c->dptr<double>(c->off_dt), dev_dt_last, c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_padded_size(cfd_ctx* c, size_t* count) {
+  cfd_status s = need(c, true, false);
+  if (s != CFD_OK) return s;
+  if (!count) return CFD_ERR_ARG;
+  *count = (size_t)c->padded_total;
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_padded_primitives(cfd_ctx* c, double* dev_out) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!dev_out) return CFD_ERR_ARG;
+  if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
+  if ((s = fill_ghosts(c, c->stA(), c->stream)) != CFD_OK) return s;
+  CellArgs a = cell_args(c);
+  a.src = c->stA();
+  a.dst = dev_out;
+  HIP_TRY(c, launch_export_padded(c->dim, a, c->max_padded, (int)c->blocks.size(), c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_set_exec(cfd_ctx* c, int mode, int use_graph) {
+  if (!c) return CFD_ERR_ARG;
+  if (mode != CFD_EXEC_BATCHED && mode != CFD_EXEC_PER_BLOCK) return fail(c, CFD_ERR_ARG, "bad exec mode");
+  c->exec_mode = mode;
+  c->use_graph = use_graph ? 1 : 0;
+  release_graph(c);
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_set_variant(cfd_ctx* c, int v) {
+  if (!c) return CFD_ERR_ARG;
+  if (v < 0 || v >= c->nvariants) return fail(c, CFD_ERR_ARG, "variant %d out of range", v);
+  c->variant = v;
+  release_graph(c);
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_autotune(cfd_ctx* c, int reps, int* chosen) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
+  if (reps < 1) reps = 1;
+  s = fill_ghosts(c, c->stA(), c->stream);
+  if (s != CFD_OK) return s;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  const int keep = c->variant;
+  int best = keep;
+  float best_ms = 1e30f;
+  for (int v = 0; v < c->nvariants; ++v) {
+    c->variant = v;
+    StageArgs a = stage_args(c);
+    a.qin = c->stA();
+    a.q0 = c->stA();
+    a.qout = c->stB();
+    a.mode = MODE_STAGE;
+    a.alpha = 0.25;
+    a.dtmin = nullptr;
+    if ((s = launch_stage_all(c, a, c->stream, false)) != CFD_OK) break;  // warm-up
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps && s == CFD_OK; ++r) s = launch_stage_all(c, a, c->stream, false);
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->variant = best;
+  release_graph(c);
+  if (chosen) *chosen = best;
+  return s;
+}
+
+extern "C" cfd_status cfd_profile(cfd_ctx* c, int enable) {
+  if (!c) return CFD_ERR_ARG;
+  c->profiling = enable != 0;
+  c->ev_used = 0;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_kernel_time(cfd_ctx* c, double* total_ms, long long* launches) {
+  if (!c) return CFD_ERR_ARG;
+  double ms = c->prof_ms;
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    HIP_TRY(c, hipEventSynchronize(c->ev_pool[i].b));
+    float t = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&t, c->ev_pool[i].a, c->ev_pool[i].b));
+    ms += t;
+  }
+  c->prof_ms = ms;
+  c->ev_used = 0;
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = c->prof_launches;
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_query(cfd_ctx* c, int what, long long* value) {
+  if (!c || !value) return CFD_ERR_ARG;
+  int nv = 0;
+  const StageVariant* vars = stage_variants(c->dim, &nv);
+  switch (what) {
+    case CFD_Q_NBLOCKS: *value = (long long)c->hblocks.size(); return CFD_OK;
+    case CFD_Q_NVAR: *value = c->nvar; return CFD_OK;
+    case CFD_Q_NVARIANTS: *value = nv; return CFD_OK;
+    case CFD_Q_VARIANT: *value = c->variant; return CFD_OK;
+    case CFD_Q_TILE_X: *value = vars[c->variant].tx; return CFD_OK;
+    case CFD_Q_TILE_Y: *value = vars[c->variant].ty; return CFD_OK;
+    default: break;
+  }
+  if (!c->finalized) return fail(c, CFD_ERR_STATE, "context is not finalized");
+  switch (what) {
+    case CFD_Q_NCELLS: *value = c->ncells; return CFD_OK;
+    case CFD_Q_NTILES: *value = (long long)c->tiles_batched[c->variant].size(); return CFD_OK;
+    case CFD_Q_NTRANSFERS: *value = (long long)c->xfers.size(); return CFD_OK;
+    case CFD_Q_NPATCHES: *value = (long long)c->patches.size(); return CFD_OK;
+    case CFD_Q_NNODES: *value = c->nnodes; return CFD_OK;
+    case CFD_Q_EXCHANGE_DOUBLES: *value = c->xbuf_doubles; return CFD_OK;
+    case CFD_Q_WORKSPACE_BYTES: *value = (long long)c->ws_bytes; return CFD_OK;
+    default: return fail(c, CFD_ERR_ARG, "unknown query %d", what);
+  }
+}

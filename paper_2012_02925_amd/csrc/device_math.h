@@ -1,0 +1,176 @@
+// Per-face and per-cell arithmetic of the Euler hot path (device functions).
+//
+// Primitive variables q = (rho, u, v[, w], p); conservative Q = (rho, rho u,
+// rho v[, rho w], rho E) with rho E = p/(gamma-1) + rho |u|^2 / 2 (Sec. 2, eq. (2)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cfd {
+
+struct Gas {
+  double gamma, gm1, igm1, g_gm1;  // gamma, gamma-1, 1/(gamma-1), gamma/(gamma-1)
+};
+
+// Limiter in slope form S(a, b) = Psi(a / b) * b (defined at b = 0), for the
+// symmetric limiters the face states reduce to q_i +- (eps/2) S(D+, D-) for
+// every kappa of eq. (flux).
+enum { LIM_NONE = 0, LIM_VANLEER = 1, LIM_VANALBADA = 2 };
+
+template <int LIM>
+__device__ __forceinline__ double slope(double a, double b, double e2) {
+  if constexpr (LIM == LIM_NONE) {
+    return b;
+  } else if constexpr (LIM == LIM_VANLEER) {
+    double aa = fabs(a), ab = fabs(b);
+    double den = aa + ab;
+    double num = a * ab + aa * b;
+    return den > 0.0 ? num / den : 0.0;
+  } else {
+    double a2 = a * a, b2 = b * b;
+    double den = a2 + b2 + 2.0 * e2;
+    double num = (b2 + e2) * a + (a2 + e2) * b;
+    return den > 0.0 ? num / den : 0.0;
+  }
+}
+
+// Per-cell slopes of eq. (flux) for the two faces of a cell along one
+// direction, from the backward and forward differences dm = q_i - q_{i-1},
+// dp = q_{i+1} - q_i:  q^L_{i+1/2} = q_i + (eps/2) sp,  q^R_{i-1/2} = q_i - (eps/2) sm.
+// Symmetric limiters: sp = sm = S(dp, dm) for every kappa.  Psi = 1 (no limiter):
+// sp = ((1-kappa) dm + (1+kappa) dp)/2, sm = ((1+kappa) dm + (1-kappa) dp)/2.
+template <int LIM>
+__device__ __forceinline__ void cell_slopes(double dm, double dp, double e2, double kap, double& sp, double& sm) {
+  if constexpr (LIM == LIM_NONE) {
+    sp = 0.5 * ((1.0 - kap) * dm + (1.0 + kap) * dp);
+    sm = 0.5 * ((1.0 + kap) * dm + (1.0 - kap) * dp);
+  } else {
+    sp = slope<LIM>(dp, dm, e2);
+    sm = sp;
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ void prim_to_cons(const double* q, const Gas& g, double* Q) {
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ke += q[1 + d] * q[1 + d];
+  Q[0] = q[0];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) Q[1 + d] = q[0] * q[1 + d];
+  Q[DIM + 1] = q[DIM + 1] * g.igm1 + 0.5 * q[0] * ke;
+}
+
+template <int DIM>
+__device__ __forceinline__ void cons_to_prim(const double* Q, const Gas& g, double* q) {
+  double ir = 1.0 / Q[0];
+  double ke = 0.0;
+  q[0] = Q[0];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    q[1 + d] = Q[1 + d] * ir;
+    ke += q[1 + d] * q[1 + d];
+  }
+  q[DIM + 1] = g.gm1 * (Q[DIM + 1] - 0.5 * Q[0] * ke);
+}
+
+// Harten-smoothed absolute value: |l| where |l| >= delta, else (l^2 + delta^2) / (2 delta).
+__device__ __forceinline__ double habs(double l, double delta, double inv2d) {
+  double a = fabs(l);
+  return a >= delta ? a : (l * l + delta * delta) * inv2d;
+}
+
+// Roe flux-difference splitting (Sec. 2; textbook rotated form) through a
+// face with area vector S (|S| = area, S/|S| = unit normal toward the right
+// state).  Output: flux times area.  efix > 0 enables Harten smoothing of all
+// three eigenvalue families with half-width efix * c~.
+template <int DIM>
+__device__ __forceinline__ void roe_flux(const double* qL, const double* qR, const double* S, const Gas& g,
+                                         double efix, double* F) {
+  constexpr int NV = DIM + 2;
+  double A2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) A2 += S[d] * S[d];
+  const double A = sqrt(A2);
+  const double iA = 1.0 / A;
+  double n[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) n[d] = S[d] * iA;
+
+  const double rL = qL[0], rR = qR[0];
+  const double pL = qL[NV - 1], pR = qR[NV - 1];
+  double vnL = 0.0, vnR = 0.0, keL = 0.0, keR = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    vnL += qL[1 + d] * n[d];
+    vnR += qR[1 + d] * n[d];
+    keL += qL[1 + d] * qL[1 + d];
+    keR += qR[1 + d] * qR[1 + d];
+  }
+  const double irL = 1.0 / rL, irR = 1.0 / rR;
+  const double HL = g.g_gm1 * pL * irL + 0.5 * keL;
+  const double HR = g.g_gm1 * pR * irR + 0.5 * keR;
+
+  // Roe averages
+  const double R = sqrt(rR * irL);
+  const double iR1 = 1.0 / (1.0 + R);
+  const double rt = R * rL;
+  double ut[DIM];
+  double q2t = 0.0, Vt = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    ut[d] = (qL[1 + d] + R * qR[1 + d]) * iR1;
+    q2t += ut[d] * ut[d];
+    Vt += ut[d] * n[d];
+  }
+  const double Ht = (HL + R * HR) * iR1;
+  const double c2t = g.gm1 * (Ht - 0.5 * q2t);
+  const double ct = sqrt(c2t);
+  const double ic2 = 1.0 / c2t;
+
+  // jumps and wave strengths
+  const double drho = rR - rL;
+  const double dp = pR - pL;
+  double du[DIM];
+  double dV = 0.0, udu = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    du[d] = qR[1 + d] - qL[1 + d];
+    dV += du[d] * n[d];
+    udu += ut[d] * du[d];
+  }
+  const double rcdV = rt * ct * dV;
+  const double a1 = 0.5 * (dp - rcdV) * ic2;
+  const double a5 = 0.5 * (dp + rcdV) * ic2;
+  const double a2 = drho - dp * ic2;
+
+  double m1, m2, m5;
+  if (efix > 0.0) {
+    const double delta = efix * ct;
+    const double inv2d = 0.5 / delta;
+    m1 = habs(Vt - ct, delta, inv2d);
+    m2 = habs(Vt, delta, inv2d);
+    m5 = habs(Vt + ct, delta, inv2d);
+  } else {
+    m1 = fabs(Vt - ct);
+    m2 = fabs(Vt);
+    m5 = fabs(Vt + ct);
+  }
+  const double w1 = m1 * a1, w5 = m5 * a5, w2 = m2 * a2, ws = m2 * rt;
+
+  // dissipation D and central part, combined per component
+  const double hA = 0.5 * A;
+  // mass
+  F[0] = hA * (rL * vnL + rR * vnR - (w1 + w2 + w5));
+  // momentum
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double Dm = w1 * (ut[d] - ct * n[d]) + w2 * ut[d] + ws * (du[d] - dV * n[d]) + w5 * (ut[d] + ct * n[d]);
+    F[1 + d] = hA * (rL * qL[1 + d] * vnL + pL * n[d] + rR * qR[1 + d] * vnR + pR * n[d] - Dm);
+  }
+  // energy
+  const double De = w1 * (Ht - ct * Vt) + w2 * 0.5 * q2t + ws * (udu - Vt * dV) + w5 * (Ht + ct * Vt);
+  F[NV - 1] = hA * (rL * HL * vnL + rR * HR * vnR - De);
+}
+
+}  // namespace cfd

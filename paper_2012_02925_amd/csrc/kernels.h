@@ -1,0 +1,61 @@
+// Launch interface between the host planner (api.hip) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cfd_internal.h"
+#include "device_math.h"
+
+namespace cfd {
+
+struct StageArgs;  // stage_kernel.h
+
+struct GhostArgs {
+  const BlockDev* blocks;
+  const TransferDev* xfers;
+  const PatchDev* patches;
+  const ChunkDev* chunks;
+  int chunk_begin;
+  double* q;              // state buffer whose ghosts are filled
+  double* buf;            // exchange buffer
+  const double* inflow;   // inflow primitive states, MAXV doubles per inflow patch
+  const double* metric;
+};
+
+struct CellArgs {
+  const BlockDev* blocks;
+  const double* src;
+  double* dst;
+  const double* metric;
+  const long long* offsets;  // export_padded: output offset per block
+  unsigned long long* dtmin;
+  int* err;
+  int flag_primitive;
+  Gas gas;
+};
+
+struct MetricArgs {
+  const BlockDev* blocks;
+  const double* nodes;
+  double* metric;
+  int* err;
+};
+
+struct StageVariant {
+  int tx, ty, kc;
+};
+
+const StageVariant* stage_variants(int dim, int* count);
+hipError_t launch_stage(int dim, int lim, int variant, const StageArgs& a, int grid, hipStream_t s);
+hipError_t launch_ghost(int dim, const GhostArgs& a, int nchunks, hipStream_t s);
+hipError_t launch_set_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
+hipError_t launch_get_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
+hipError_t launch_cell_dt(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
+hipError_t launch_export_padded(int dim, const CellArgs& a, long long max_padded, int nblocks, hipStream_t s);
+hipError_t launch_metrics(int dim, const MetricArgs& a, long long max_pos, int nblocks, hipStream_t s);
+hipError_t launch_dt_promote(double* dt, unsigned long long* dtmin, double cfl, int promote, double* out,
+                             hipStream_t s);
+hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
+hipError_t launch_copy_dt(const double* src, double* dst, hipStream_t s);
+
+}  // namespace cfd

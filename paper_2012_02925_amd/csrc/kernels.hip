@@ -1,0 +1,459 @@
+// Device kernels of the Euler hot path and their host-side launchers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "cfd_internal.h"
+#include "device_math.h"
+#include "kernels.h"
+#include "stage_kernel.h"
+
+namespace cfd {
+
+// ---------------------------------------------------------------------------
+// ghost fill: pack / physical patches / unpack (Sec. 2 ghost cells; Sec. 7.2
+// V1 pack/unpack and V5 persistent per-connection buffers)
+
+template <int DIM>
+__device__ __forceinline__ void mirror_velocity(double* q, const double* S) {
+  double s2 = 0.0, un = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    s2 += S[d] * S[d];
+    un += q[1 + d] * S[d];
+  }
+  const double f = 2.0 * un / s2;  // 2 (u . n) n with n = S/|S|
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) q[1 + d] -= f * S[d];
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(CHUNK) ghost_kernel(GhostArgs a) {
+  constexpr int NV = DIM + 2;
+  using ML = MetricLayout<DIM>;
+  const ChunkDev ch = a.chunks[a.chunk_begin + blockIdx.x];
+  const int e = ch.start + threadIdx.x;
+  if (threadIdx.x >= ch.count) return;
+  if (ch.kind == 0 || ch.kind == 2) {
+    const TransferDev x = a.xfers[ch.item];
+    const int per_layer = x.len0 * x.len1;
+    const int cnt = 2 * per_layer;
+    const int layer = e / per_layer;
+    const int r = e - layer * per_layer;
+    const int r1 = r % x.len0, r2 = r / x.len0;
+    double* seg = a.buf + x.buf;
+    if (ch.kind == 0) {
+      int d1, d2;
+      orient_map(x.orient, r1, r2, x.dlen0, x.dlen1, d1, d2);
+      const BlockDev& B = a.blocks[x.dblock];
+      int i, j, k;
+      face_cell(B, DIM, x.dface, layer, false, x.dlo0 + d1, x.dlo1 + d2, i, j, k);
+      const double* q = a.q + B.origin + pidx(B, i, j, k);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) seg[v * cnt + e] = q[v * B.vstride];
+    } else {
+      const BlockDev& B = a.blocks[x.rblock];
+      int i, j, k;
+      face_cell(B, DIM, x.rface, layer, true, x.rlo0 + r1, x.rlo1 + r2, i, j, k);
+      double* q = a.q + B.origin + pidx(B, i, j, k);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) q[v * B.vstride] = seg[v * cnt + e];
+    }
+    return;
+  }
+  // physical patch
+  const PatchDev p = a.patches[ch.item];
+  const int per_layer = p.len0 * p.len1;
+  const int layer = e / per_layer;
+  const int r = e - layer * per_layer;
+  const int t1 = p.lo0 + r % p.len0, t2 = p.lo1 + r / p.len0;
+  const BlockDev& B = a.blocks[p.block];
+  const long long vs = B.vstride;
+  int gi, gj, gk;
+  face_cell(B, DIM, p.face, layer, true, t1, t2, gi, gj, gk);
+  double* base = a.q + B.origin;
+  double g[NV];
+  if (p.kind == PK_SUP_INFLOW) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) g[v] = a.inflow[p.param * MAXV + v];
+  } else {
+    int si, sj, sk;
+    face_cell(B, DIM, p.face, p.kind == PK_SLIP_WALL ? layer : 0, false, t1, t2, si, sj, sk);
+    const long long s = pidx(B, si, sj, sk);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) g[v] = base[v * vs + s];
+    if (p.kind == PK_SLIP_WALL) {
+      // area vector of the boundary face itself
+      int fi, fj, fk;
+      face_cell(B, DIM, p.face, 0, (p.face & 1) != 0, t1, t2, fi, fj, fk);
+      const long long fidx = pidx(B, fi, fj, fk);
+      const double* met = a.metric + B.morigin;
+      double S[DIM];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) S[c] = met[ML::S(p.face >> 1, c) * vs + fidx];
+      mirror_velocity<DIM>(g, S);
+    }
+  }
+  const long long gidx = pidx(B, gi, gj, gk);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) base[v * vs + gidx] = g[v];
+}
+
+// ---------------------------------------------------------------------------
+// per-cell kernels over the packed layout (grid.y = block)
+
+__device__ __forceinline__ bool cell_of(const BlockDev& B, long long c, int& i, int& j, int& k) {
+  const long long n = (long long)B.ni * B.nj * B.nk;
+  if (c >= n) return false;
+  i = (int)(c % B.ni);
+  const long long r = c / B.ni;
+  j = (int)(r % B.nj);
+  k = (int)(r / B.nj);
+  return true;
+}
+
+template <int DIM>
+__global__ void set_state_kernel(CellArgs a) {
+  constexpr int NV = DIM + 2;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!cell_of(B, c, i, j, k)) return;
+  double in[NV], q[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) in[v] = a.src[v * B.ncell_total + B.packed + c];
+  if (a.flag_primitive) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v] = in[v];
+  } else {
+    cons_to_prim<DIM>(in, a.gas, q);
+  }
+  bool ok = q[0] > 0.0 && q[NV - 1] > 0.0 && isfinite(q[0]) && isfinite(q[NV - 1]);
+#pragma unroll
+  for (int v = 1; v < NV - 1; ++v) ok = ok && isfinite(q[v]);
+  if (!ok) atomicOr(a.err, 1);
+  double* dst = a.dst + B.origin + pidx(B, i, j, k);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dst[v * B.vstride] = q[v];
+}
+
+template <int DIM>
+__global__ void get_state_kernel(CellArgs a) {
+  constexpr int NV = DIM + 2;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!cell_of(B, c, i, j, k)) return;
+  const double* src = a.src + B.origin + pidx(B, i, j, k);
+  double q[NV], Q[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q[v] = src[v * B.vstride];
+  if (a.flag_primitive) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Q[v] = q[v];
+  } else {
+    prim_to_cons<DIM>(q, a.gas, Q);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) a.dst[v * B.ncell_total + B.packed + c] = Q[v];
+}
+
+// Omega / lambda of every interior cell, reduced to one minimum (bits of a
+// positive double, atomicMin on the unsigned pattern is an exact min).
+template <int DIM>
+__global__ void __launch_bounds__(256) cell_dt_kernel(CellArgs a) {
+  constexpr int NV = DIM + 2;
+  using ML = MetricLayout<DIM>;
+  __shared__ double red[4];
+  const BlockDev B = a.blocks[blockIdx.y];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double m = 1.0e300;
+  int i, j, k;
+  if (cell_of(B, c, i, j, k)) {
+    const long long ci = pidx(B, i, j, k);
+    const double* q = a.src + B.origin + ci;
+    const double* met = a.metric + B.morigin + ci;
+    const long long vs = B.vstride;
+    double w[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = q[v * vs];
+    const double cs = sqrt(a.gas.gamma * w[NV - 1] / w[0]);
+    double lam = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const long long step = d == 0 ? 1 : (d == 1 ? (long long)B.pi : (long long)B.pi * B.pj);
+      double un = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < DIM; ++cc) {
+        const double sb = 0.5 * (met[ML::S(d, cc) * vs] + met[ML::S(d, cc) * vs + step]);
+        un += w[1 + cc] * sb;
+        s2 += sb * sb;
+      }
+      lam += fabs(un) + cs * sqrt(s2);
+    }
+    m = 1.0 / (lam * met[ML::INVVOL * vs]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    atomicMin(a.dtmin, (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+// dt <- cfl * min (when promote) ; min <- +inf
+__global__ void dt_promote_kernel(double* dt, unsigned long long* dtmin, double cfl, int promote, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double m = __longlong_as_double((long long)*dtmin);
+    if (promote) dt[0] = cfl * m;
+    if (out) out[0] = cfl * m;
+    if (promote) *dtmin = (unsigned long long)__double_as_longlong(INFINITY);
+  }
+}
+
+__global__ void set_u64_kernel(unsigned long long* p, unsigned long long v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void copy_dt_kernel(const double* src, double* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
+}
+
+// ---------------------------------------------------------------------------
+// metrics from nodes (setup)
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <int DIM>
+__global__ void metrics_kernel(MetricArgs a) {
+  using ML = MetricLayout<DIM>;
+  const BlockDev B = a.blocks[blockIdx.y];
+  // positions (i, j, k) in [0, ni] x [0, nj] x [0, nk] (k = 0 only in 2D)
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ei = B.ni + 1, ej = B.nj + 1, ek = DIM == 3 ? B.nk + 1 : 1;
+  if (c >= (long long)ei * ej * ek) return;
+  const int i = (int)(c % ei);
+  const int j = (int)((c / ei) % ej);
+  const int k = (int)(c / ((long long)ei * ej));
+  const long long nn = B.nnode_total;
+  const int ni1 = B.ni + 1, nj1 = B.nj + 1;
+  auto X = [&](int cc, int ii, int jj, int kk) -> double {
+    return a.nodes[cc * nn + B.node0 + ((long long)kk * nj1 + jj) * ni1 + ii];
+  };
+  double* met = a.metric + B.morigin;
+  const long long vs = B.vstride;
+  const long long ci = pidx(B, i, j, k);
+  if constexpr (DIM == 2) {
+    if (j < B.nj) {  // i-face from node (i,j) to (i,j+1)
+      const double dx = X(0, i, j + 1, 0) - X(0, i, j, 0), dy = X(1, i, j + 1, 0) - X(1, i, j, 0);
+      met[ML::S(0, 0) * vs + ci] = dy;
+      met[ML::S(0, 1) * vs + ci] = -dx;
+    }
+    if (i < B.ni) {  // j-face from node (i,j) to (i+1,j)
+      const double dx = X(0, i + 1, j, 0) - X(0, i, j, 0), dy = X(1, i + 1, j, 0) - X(1, i, j, 0);
+      met[ML::S(1, 0) * vs + ci] = -dy;
+      met[ML::S(1, 1) * vs + ci] = dx;
+    }
+    if (i < B.ni && j < B.nj) {
+      const double d1x = X(0, i + 1, j + 1, 0) - X(0, i, j, 0), d1y = X(1, i + 1, j + 1, 0) - X(1, i, j, 0);
+      const double d2x = X(0, i, j + 1, 0) - X(0, i + 1, j, 0), d2y = X(1, i, j + 1, 0) - X(1, i + 1, j, 0);
+      const double vol = 0.5 * (d1x * d2y - d1y * d2x);
+      if (!(vol > 0.0) || !isfinite(vol)) atomicOr(a.err, 1);
+      met[ML::INVVOL * vs + ci] = 1.0 / vol;
+    }
+  } else {
+    auto P = [&](int ii, int jj, int kk, double* p) {
+      p[0] = X(0, ii, jj, kk);
+      p[1] = X(1, ii, jj, kk);
+      p[2] = X(2, ii, jj, kk);
+    };
+    // area vector 1/2 (c - a) x (d - b) of quad a b c d, plus the mean node
+    auto quad = [&](const double* pa, const double* pb, const double* pc, const double* pd, double* S, double* m) {
+      double u[3], w[3];
+      for (int q = 0; q < 3; ++q) {
+        u[q] = pc[q] - pa[q];
+        w[q] = pd[q] - pb[q];
+        m[q] = 0.25 * (pa[q] + pb[q] + pc[q] + pd[q]);
+      }
+      cross3(u, w, S);
+      for (int q = 0; q < 3; ++q) S[q] *= 0.5;
+    };
+    double pa[3], pb[3], pc[3], pd[3], S[3], m[3];
+    if (j < B.nj && k < B.nk) {  // i-face: (i,j,k) (i,j+1,k) (i,j+1,k+1) (i,j,k+1)
+      P(i, j, k, pa); P(i, j + 1, k, pb); P(i, j + 1, k + 1, pc); P(i, j, k + 1, pd);
+      quad(pa, pb, pc, pd, S, m);
+      for (int q = 0; q < 3; ++q) met[ML::S(0, q) * vs + ci] = S[q];
+    }
+    if (i < B.ni && k < B.nk) {  // j-face: (i,j,k) (i,j,k+1) (i+1,j,k+1) (i+1,j,k)
+      P(i, j, k, pa); P(i, j, k + 1, pb); P(i + 1, j, k + 1, pc); P(i + 1, j, k, pd);
+      quad(pa, pb, pc, pd, S, m);
+      for (int q = 0; q < 3; ++q) met[ML::S(1, q) * vs + ci] = S[q];
+    }
+    if (i < B.ni && j < B.nj) {  // k-face: (i,j,k) (i+1,j,k) (i+1,j+1,k) (i,j+1,k)
+      P(i, j, k, pa); P(i + 1, j, k, pb); P(i + 1, j + 1, k, pc); P(i, j + 1, k, pd);
+      quad(pa, pb, pc, pd, S, m);
+      for (int q = 0; q < 3; ++q) met[ML::S(2, q) * vs + ci] = S[q];
+    }
+    if (i < B.ni && j < B.nj && k < B.nk) {
+      // volume = 1/3 sum_f xbar_f . S_f (outward); low faces enter with a minus sign
+      double vol = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        for (int side = 0; side < 2; ++side) {
+          const int ii = i + (d == 0 ? side : 0), jj = j + (d == 1 ? side : 0), kk = k + (d == 2 ? side : 0);
+          if (d == 0) {
+            P(ii, jj, kk, pa); P(ii, jj + 1, kk, pb); P(ii, jj + 1, kk + 1, pc); P(ii, jj, kk + 1, pd);
+          } else if (d == 1) {
+            P(ii, jj, kk, pa); P(ii, jj, kk + 1, pb); P(ii + 1, jj, kk + 1, pc); P(ii + 1, jj, kk, pd);
+          } else {
+            P(ii, jj, kk, pa); P(ii + 1, jj, kk, pb); P(ii + 1, jj + 1, kk, pc); P(ii, jj + 1, kk, pd);
+          }
+          quad(pa, pb, pc, pd, S, m);
+          const double f = m[0] * S[0] + m[1] * S[1] + m[2] * S[2];
+          vol += side ? f : -f;
+        }
+      }
+      vol *= (1.0 / 3.0);
+      if (!(vol > 0.0) || !isfinite(vol)) atomicOr(a.err, 1);
+      met[ML::INVVOL * vs + ci] = 1.0 / vol;
+    }
+  }
+}
+
+// padded export of a state buffer: block after block, [var][k+2][j+2][i+2]
+template <int DIM>
+__global__ void export_padded_kernel(CellArgs a) {
+  constexpr int NV = DIM + 2;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const int ei = B.ni + 4, ej = B.nj + 4, ek = DIM == 3 ? B.nk + 4 : 1;
+  const long long n = (long long)ei * ej * ek;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int i = (int)(c % ei) - 2;
+  const int j = (int)((c / ei) % ej) - 2;
+  const int k = (int)(c / ((long long)ei * ej)) - (DIM == 3 ? 2 : 0);
+  const double* src = a.src + B.origin + pidx(B, i, j, k);
+  double* dst = a.dst + a.offsets[blockIdx.y];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) dst[v * n + c] = src[v * B.vstride];
+}
+
+// ---------------------------------------------------------------------------
+// stage kernel variants
+
+template <int DIM, int LIM, int TX, int TY, int KC>
+static hipError_t launch_stage_t(const StageArgs& a, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC>), dim3(grid), dim3(TX * TY), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int DIM, int TX, int TY, int KC>
+static hipError_t launch_stage_lim(int lim, const StageArgs& a, int grid, hipStream_t s) {
+  switch (lim) {
+    case LIM_NONE: return launch_stage_t<DIM, LIM_NONE, TX, TY, KC>(a, grid, s);
+    case LIM_VANLEER: return launch_stage_t<DIM, LIM_VANLEER, TX, TY, KC>(a, grid, s);
+    default: return launch_stage_t<DIM, LIM_VANALBADA, TX, TY, KC>(a, grid, s);
+  }
+}
+
+const StageVariant* stage_variants(int dim, int* count) {
+  static const StageVariant v2[] = {{64, 4, 1}, {32, 8, 1}, {16, 16, 1}};
+  static const StageVariant v3[] = {{64, 4, 32}, {32, 8, 32}, {32, 8, 64}};
+  *count = 3;
+  return dim == 2 ? v2 : v3;
+}
+
+hipError_t launch_stage(int dim, int lim, int variant, const StageArgs& a, int grid, hipStream_t s) {
+  if (dim == 2) {
+    switch (variant) {
+      case 0: return launch_stage_lim<2, 64, 4, 1>(lim, a, grid, s);
+      case 1: return launch_stage_lim<2, 32, 8, 1>(lim, a, grid, s);
+      default: return launch_stage_lim<2, 16, 16, 1>(lim, a, grid, s);
+    }
+  }
+  switch (variant) {
+    case 0: return launch_stage_lim<3, 64, 4, 32>(lim, a, grid, s);
+    case 1: return launch_stage_lim<3, 32, 8, 32>(lim, a, grid, s);
+    default: return launch_stage_lim<3, 32, 8, 64>(lim, a, grid, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+hipError_t launch_ghost(int dim, const GhostArgs& a, int nchunks, hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
+  if (dim == 2)
+    hipLaunchKernelGGL(ghost_kernel<2>, dim3(nchunks), dim3(CHUNK), 0, s, a);
+  else
+    hipLaunchKernelGGL(ghost_kernel<3>, dim3(nchunks), dim3(CHUNK), 0, s, a);
+  return hipGetLastError();
+}
+
+static dim3 cell_grid(long long max_cells, int nblocks) {
+  return dim3((unsigned)((max_cells + 255) / 256), (unsigned)nblocks);
+}
+
+hipError_t launch_set_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(set_state_kernel<2>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(set_state_kernel<3>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(get_state_kernel<2>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(get_state_kernel<3>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_dt(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(cell_dt_kernel<2>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(cell_dt_kernel<3>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_padded(int dim, const CellArgs& a, long long max_padded, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(export_padded_kernel<2>, cell_grid(max_padded, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(export_padded_kernel<3>, cell_grid(max_padded, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_metrics(int dim, const MetricArgs& a, long long max_pos, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(metrics_kernel<2>, cell_grid(max_pos, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(metrics_kernel<3>, cell_grid(max_pos, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt_promote(double* dt, unsigned long long* dtmin, double cfl, int promote, double* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(dt_promote_kernel, dim3(1), dim3(64), 0, s, dt, dtmin, cfl, promote, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s) {
+  hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_dt(const double* src, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(copy_dt_kernel, dim3(1), dim3(64), 0, s, src, dst);
+  return hipGetLastError();
+}
+
+}  // namespace cfd
