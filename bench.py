@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 1 GiB (torch copy kernel) to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs the whole workload on one GPU; --gpus %d is not supported "
@@ -117,6 +119,15 @@ def main():
     from paper_2012_02925_amd.solver import Solver
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
     case = make_case(args.workload, args.n)
     print("[bench] workload %s, %d cells, building" % (case.name, case.ncells), file=sys.stderr, flush=True)
     s = Solver.from_case(case, device="cuda:0")

@@ -15,6 +15,9 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
+    # contract a*b+c into FMA only within one source expression, so the
+    # same expression yields the same bits wherever it is inlined
+    "-ffp-contract=on",
     "-shared",
     # keep hipcc from forming packed FP32 instructions (FP64 code, but the
     # setup/reduction paths touch float helpers)

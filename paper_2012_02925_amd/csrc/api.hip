@@ -666,6 +666,7 @@ static StageArgs stage_args(cfd_ctx* c) {
   a.half_eps = 0.5 * c->cfg.muscl_eps;
   a.kappa = c->cfg.muscl_kappa;
   a.efix = c->cfg.efix;
+  a.half_inv_efix = c->cfg.efix > 0.0 ? 0.5 / c->cfg.efix : 0.0;
   for (int v = 0; v < MAXV; ++v) a.e2[v] = c->cfg.lim_eps[v] * c->cfg.lim_eps[v];
   return a;
 }

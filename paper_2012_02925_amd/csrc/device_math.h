@@ -12,10 +12,35 @@ struct Gas {
   double gamma, gm1, igm1, g_gm1;  // gamma, gamma-1, 1/(gamma-1), gamma/(gamma-1)
 };
 
+// Reciprocal and reciprocal square root from the hardware estimates refined
+// by two Newton steps each (about one unit in the last place, not correctly
+// rounded), in place of the IEEE division / square-root sequences.  Arguments
+// are positive normal numbers on every call site.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double hy = 0.5 * y;
+  double e = fma(-(x * y), y, 1.0);
+  y = fma(hy, e, y);
+  hy = 0.5 * y;
+  e = fma(-(x * y), y, 1.0);
+  return fma(hy, e, y);
+}
+
 // Limiter in slope form S(a, b) = Psi(a / b) * b (defined at b = 0), for the
 // symmetric limiters the face states reduce to q_i +- (eps/2) S(D+, D-) for
-// every kappa of eq. (flux).
+// every kappa of eq. (flux).  A denominator below 1e-250 returns 0: the
+// differences are then below 1e-250 (van Leer) or 1e-125 (van Albada without
+// regularisation) and so is the exact slope.
 enum { LIM_NONE = 0, LIM_VANLEER = 1, LIM_VANALBADA = 2 };
+constexpr double SLOPE_TINY = 1e-250;
 
 template <int LIM>
 __device__ __forceinline__ double slope(double a, double b, double e2) {
@@ -25,12 +50,12 @@ __device__ __forceinline__ double slope(double a, double b, double e2) {
     double aa = fabs(a), ab = fabs(b);
     double den = aa + ab;
     double num = a * ab + aa * b;
-    return den > 0.0 ? num / den : 0.0;
+    return den > SLOPE_TINY ? num * rcp(den) : 0.0;
   } else {
     double a2 = a * a, b2 = b * b;
     double den = a2 + b2 + 2.0 * e2;
     double num = (b2 + e2) * a + (a2 + e2) * b;
-    return den > 0.0 ? num / den : 0.0;
+    return den > SLOPE_TINY ? num * rcp(den) : 0.0;
   }
 }
 
@@ -63,7 +88,7 @@ __device__ __forceinline__ void prim_to_cons(const double* q, const Gas& g, doub
 
 template <int DIM>
 __device__ __forceinline__ void cons_to_prim(const double* Q, const Gas& g, double* q) {
-  double ir = 1.0 / Q[0];
+  double ir = rcp(Q[0]);
   double ke = 0.0;
   q[0] = Q[0];
 #pragma unroll
@@ -86,13 +111,13 @@ __device__ __forceinline__ double habs(double l, double delta, double inv2d) {
 // three eigenvalue families with half-width efix * c~.
 template <int DIM>
 __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, const double* S, const Gas& g,
-                                         double efix, double* F) {
+                                         double efix, double half_inv_efix, double* F) {
   constexpr int NV = DIM + 2;
   double A2 = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) A2 += S[d] * S[d];
-  const double A = sqrt(A2);
-  const double iA = 1.0 / A;
+  const double iA = rsq(A2);  // 1/|S|
+  const double A = A2 * iA;
   double n[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) n[d] = S[d] * iA;
@@ -107,13 +132,14 @@ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, con
     keL += qL[1 + d] * qL[1 + d];
     keR += qR[1 + d] * qR[1 + d];
   }
-  const double irL = 1.0 / rL, irR = 1.0 / rR;
+  const double irL = rcp(rL), irR = rcp(rR);
   const double HL = g.g_gm1 * pL * irL + 0.5 * keL;
   const double HR = g.g_gm1 * pR * irR + 0.5 * keR;
 
-  // Roe averages
-  const double R = sqrt(rR * irL);
-  const double iR1 = 1.0 / (1.0 + R);
+  // Roe averages, R = sqrt(rho_R / rho_L)
+  const double ratio = rR * irL;
+  const double R = ratio * rsq(ratio);
+  const double iR1 = rcp(1.0 + R);
   const double rt = R * rL;
   double ut[DIM];
   double q2t = 0.0, Vt = 0.0;
@@ -125,8 +151,9 @@ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, con
   }
   const double Ht = (HL + R * HR) * iR1;
   const double c2t = g.gm1 * (Ht - 0.5 * q2t);
-  const double ct = sqrt(c2t);
-  const double ic2 = 1.0 / c2t;
+  const double ict = rsq(c2t);  // 1/c~
+  const double ct = c2t * ict;
+  const double ic2 = ict * ict;
 
   // jumps and wave strengths
   const double drho = rR - rL;
@@ -147,7 +174,7 @@ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, con
   double m1, m2, m5;
   if (efix > 0.0) {
     const double delta = efix * ct;
-    const double inv2d = 0.5 / delta;
+    const double inv2d = half_inv_efix * ict;  // 1 / (2 delta)
     m1 = habs(Vt - ct, delta, inv2d);
     m2 = habs(Vt, delta, inv2d);
     m5 = habs(Vt + ct, delta, inv2d);
@@ -160,15 +187,12 @@ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, con
 
   // dissipation D and central part, combined per component
   const double hA = 0.5 * A;
-  // mass
   F[0] = hA * (rL * vnL + rR * vnR - (w1 + w2 + w5));
-  // momentum
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const double Dm = w1 * (ut[d] - ct * n[d]) + w2 * ut[d] + ws * (du[d] - dV * n[d]) + w5 * (ut[d] + ct * n[d]);
     F[1 + d] = hA * (rL * qL[1 + d] * vnL + pL * n[d] + rR * qR[1 + d] * vnR + pR * n[d] - Dm);
   }
-  // energy
   const double De = w1 * (Ht - ct * Vt) + w2 * 0.5 * q2t + ws * (udu - Vt * dV) + w5 * (Ht + ct * Vt);
   F[NV - 1] = hA * (rL * HL * vnL + rR * HR * vnR - De);
 }

@@ -3,21 +3,23 @@
 // One workgroup owns a TX x TY tile of cells in the (i, j) plane of a block
 // and, in 3D, marches along k over KC planes.  Per plane:
 //   1. primitive values of the plane with a two-cell halo in i and j are
-//      staged in LDS (ghost cells included; the 3D own column comes from a
-//      register queue along k);
-//   2. limited slopes of eq. (flux) (slope form; one per cell and direction
-//      for the symmetric limiters, a high-face/low-face pair without a
-//      limiter) are computed once per cell into LDS;
-//   3. the Roe flux is computed once per face of the tile (faces on the tile
-//      edge are shared with the neighbour tile), the wall override of
+//      staged in LDS (ghost cells included; in 3D the tile's own cells come
+//      from a register queue along k);
+//   2. the limited slopes of eq. (flux) (slope form; one per cell and
+//      direction for the symmetric limiters, a high-face/low-face pair without
+//      a limiter) are computed once per cell into LDS;
+//   3. the Roe flux is computed once per i- and j-face of the tile (faces on
+//      the tile edge are shared with the neighbour tile), the wall override of
 //      Sec. 7.2 V7 applied on slip-wall faces, and stored in LDS;
-//   4. every cell sums its face fluxes, divides by its volume and either
+//   4. every cell sums its face fluxes, scales by its inverse volume and either
 //      writes the residual or applies the stage update
 //      Q^(k) = Q^(0) - alpha dt R(Q^(k-1)) (Sec. 2, M-stage Runge-Kutta) and
 //      stores the new primitive state; the last stage of a step also reduces
 //      Omega / lambda for the next CFL time step.
-// The k direction keeps (q_k, q_k+1, q_k+2, slopes, F_k-1/2) in registers so
-// every k-face flux is computed once.
+// Steps 2 and 3 run the i- and j-items of a plane as one flattened list with a
+// single code path (per-lane addressing), so a wavefront never diverges
+// between directions.  The k direction keeps (q_k, q_k+1, q_k+2, slopes,
+// F_k-1/2) in registers so every k-face flux is computed once.
 #pragma once
 
 #include "cfd_internal.h"
@@ -46,13 +48,11 @@ struct StageArgs {
   double half_eps;       // muscl eps / 2
   double kappa;          // muscl kappa (used only without a limiter)
   double efix;
+  double half_inv_efix;  // 0.5 / efix (0 when efix = 0)
   double e2[MAXV];       // van Albada regularisation squared
 };
 
-template <int DIM>
-__device__ __forceinline__ double wall_pressure(double p0, double p1) {
-  return 1.5 * p0 - 0.5 * p1;
-}
+__device__ __forceinline__ double wall_pressure(double p0, double p1) { return 1.5 * p0 - 0.5 * p1; }
 
 // true if face `face` of block b at tangential position (t1, t2) is a slip wall
 __device__ __forceinline__ bool is_wall(const StageArgs& a, int b, int face, int t1, int t2) {
@@ -77,16 +77,16 @@ template <int DIM, int LIM, int TX, int TY, int KC>
 __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
   constexpr int NV = DIM + 2;
   constexpr int NT = TX * TY;
-  constexpr int LX = TX + 4, LY = TY + 4;
+  constexpr int LX = TX + 4, LY = TY + 4, LP = LX * LY;
   // two slopes per cell only when Psi = 1 (the kappa-form is not symmetric there)
   constexpr int NS = LIM == LIM_NONE ? 2 : 1;
+  constexpr int NSX = (TX + 2) * TY, NSY = TX * (TY + 2), NSL = NSX + NSY;  // slope items
+  constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1), NFL = NFX + NFY;  // face items
   using ML = MetricLayout<DIM>;
 
-  __shared__ double sq[NV][LY][LX];          // plane primitives with halo
-  __shared__ double ssx[NS][NV][TY][TX + 2];  // i-slopes (+, -), cells i0-1 .. i0+TX
-  __shared__ double ssy[NS][NV][TY + 2][TX];  // j-slopes (+, -), cells j0-1 .. j0+TY
-  __shared__ double sfx[NV][TY][TX + 1];     // i-face fluxes, faces i0 .. i0+TX
-  __shared__ double sfy[NV][TY + 1][TX];     // j-face fluxes, faces j0 .. j0+TY
+  __shared__ double sq[NV][LP];        // plane primitives with halo, [ly][lx]
+  __shared__ double sl[NS][NV][NSL];   // slopes: i-items [r][c] (c: cells i0-1..i0+TX), then j-items
+  __shared__ double fl[NV][NFL];       // fluxes: i-faces [r][f] (f: faces i0..i0+TX), then j-faces [f][c]
   __shared__ double sred[NT / 64];
 
   const int tid = threadIdx.x;
@@ -98,6 +98,7 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
   for (int v = 0; v < NV; ++v) e2[v] = a.e2[v];
   const double dt = (a.mode == MODE_STAGE) ? *a.dt : 0.0;
   const double adt = a.alpha * dt;
+  const bool q0_is_qin = a.q0 == a.qin;
   double my_min = 1.0e300;
 
   for (int t = a.tile_begin + blockIdx.x; t < a.tile_end; t += gridDim.x) {
@@ -116,13 +117,19 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
     // slopes of k (scp/scm) and k+1 (snp/snm), pressure of k-1 (pprev).
     // The same three steps serve the two-step prologue and the march, so
     // every k-face flux is formed by identical code wherever it is computed.
-    double qc[NV], qn[NV], qnn[NV], scp[NV], scm[NV], snp[NV], snm[NV], fzlo[NV], fzhi[NV];
+    double qc[NV], qn[NV], qnn[NV], scp[NV], scm[NS == 2 ? NV : 1], snp[NV], snm[NS == 2 ? NV : 1];
+    double fzlo[NV], fzhi[NV];
     double pprev = 0.0;
     auto zload_slope = [&](int k) {  // q(k+2) and the slopes of cell k+1
 #pragma unroll
       for (int v = 0; v < NV; ++v) qnn[v] = qin[v * vs + pidx(B, i, j, k + 2)];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) cell_slopes<LIM>(qn[v] - qc[v], qnn[v] - qn[v], e2[v], kap, snp[v], snm[v]);
+      for (int v = 0; v < NV; ++v) {
+        double sp, sm;
+        cell_slopes<LIM>(qn[v] - qc[v], qnn[v] - qn[v], e2[v], kap, sp, sm);
+        snp[v] = sp;
+        if constexpr (NS == 2) snm[v] = sm;
+      }
     };
     auto zflux = [&](int k, double* F) {  // flux through the k-face k+1 (between cells k and k+1)
       const int kf = k + 1;
@@ -130,17 +137,20 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) S[c] = met[ML::S(2, c) * vs + pidx(B, i, j, kf)];
       if (kf == 0 && (B.wall_mask & (1 << 4)) && is_wall(a, tile.block, 4, i, j)) {
-        wall_flux<3>(wall_pressure<3>(qn[NV - 1], qnn[NV - 1]), S, F);
+        wall_flux<3>(wall_pressure(qn[NV - 1], qnn[NV - 1]), S, F);
       } else if (kf == B.nk && (B.wall_mask & (1 << 5)) && is_wall(a, tile.block, 5, i, j)) {
-        wall_flux<3>(wall_pressure<3>(qc[NV - 1], pprev), S, F);
+        wall_flux<3>(wall_pressure(qc[NV - 1], pprev), S, F);
       } else {
         double L[NV], R[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           L[v] = qc[v] + he * scp[v];
-          R[v] = qn[v] - he * snm[v];
+          if constexpr (NS == 2)
+            R[v] = qn[v] - he * snm[v];
+          else
+            R[v] = qn[v] - he * snp[v];
         }
-        roe_flux<3>(L, R, S, a.gas, a.efix, F);
+        roe_flux<3>(L, R, S, a.gas, a.efix, a.half_inv_efix, F);
       }
     };
     auto zrotate = [&]() {
@@ -150,7 +160,7 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
         qc[v] = qn[v];
         qn[v] = qnn[v];
         scp[v] = snp[v];
-        scm[v] = snm[v];
+        if constexpr (NS == 2) scm[v] = snm[v];
       }
     };
     if constexpr (DIM == 3) {
@@ -170,116 +180,116 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
 
     for (int k = kbeg; k < kend; ++k) {
       if constexpr (DIM == 3) {
-        if (own) {
-          zload_slope(k);
-          zflux(k, fzhi);
-        }
+        if (own) zload_slope(k);
       }
 
       // ---- 1. stage the plane with its halo in LDS ----------------------
       if (DIM == 3 && own) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sq[v][ty + 2][tx + 2] = qc[v];
+        for (int v = 0; v < NV; ++v) sq[v][(ty + 2) * LX + tx + 2] = qc[v];
       } else if (i <= B.ni + 1 && j <= B.nj + 1) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sq[v][ty + 2][tx + 2] = qin[v * vs + pidx(B, i, j, k)];
+        for (int v = 0; v < NV; ++v) sq[v][(ty + 2) * LX + tx + 2] = qin[v * vs + pidx(B, i, j, k)];
       }
       // halo ring without corners: 2 rows above/below (TX wide), 2 columns left/right (TY tall)
       for (int e = tid; e < 4 * TX + 4 * TY; e += NT) {
         int lx, ly;
         if (e < 4 * TX) {
-          int r = e / TX;
+          const int r = e / TX;
           lx = 2 + e % TX;
           ly = r < 2 ? r : TY + r;  // rows 0,1 and TY+2, TY+3
         } else {
-          int e2i = e - 4 * TX;
-          int c = e2i & 3;
+          const int e2i = e - 4 * TX;
+          const int c = e2i & 3;
           ly = 2 + (e2i >> 2);
           lx = c < 2 ? c : TX + c;  // columns 0,1 and TX+2, TX+3
         }
         const int ii = i0 - 2 + lx, jj = j0 - 2 + ly;
         if (ii <= B.ni + 1 && jj <= B.nj + 1) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) sq[v][ly][lx] = qin[v * vs + pidx(B, ii, jj, k)];
+          for (int v = 0; v < NV; ++v) sq[v][ly * LX + lx] = qin[v * vs + pidx(B, ii, jj, k)];
         }
       }
       __syncthreads();
 
-      // ---- 2. slopes ------------------------------------------------------
-      for (int e = tid; e < (TX + 2) * TY; e += NT) {
-        const int c = e % (TX + 2), r = e / (TX + 2);
-        const int lx = c + 1, ly = r + 2;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          double sp, sm;
-          cell_slopes<LIM>(sq[v][ly][lx] - sq[v][ly][lx - 1], sq[v][ly][lx + 1] - sq[v][ly][lx], e2[v], kap, sp, sm);
-          ssx[0][v][r][c] = sp;
-          if constexpr (NS == 2) ssx[NS - 1][v][r][c] = sm;
+      // ---- 2. slopes: i-items then j-items, one code path -----------------
+      for (int e = tid; e < NSL; e += NT) {
+        int p, st;
+        if (e < NSX) {
+          const int c = e % (TX + 2), r = e / (TX + 2);
+          p = (r + 2) * LX + c + 1;
+          st = 1;
+        } else {
+          const int e2i = e - NSX;
+          const int c = e2i % TX, r = e2i / TX;
+          p = (r + 1) * LX + c + 2;
+          st = LX;
         }
-      }
-      for (int e = tid; e < TX * (TY + 2); e += NT) {
-        const int c = e % TX, r = e / TX;
-        const int lx = c + 2, ly = r + 1;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double sp, sm;
-          cell_slopes<LIM>(sq[v][ly][lx] - sq[v][ly - 1][lx], sq[v][ly + 1][lx] - sq[v][ly][lx], e2[v], kap, sp, sm);
-          ssy[0][v][r][c] = sp;
-          if constexpr (NS == 2) ssy[NS - 1][v][r][c] = sm;
+          cell_slopes<LIM>(sq[v][p] - sq[v][p - st], sq[v][p + st] - sq[v][p], e2[v], kap, sp, sm);
+          sl[0][v][e] = sp;
+          if constexpr (NS == 2) sl[NS - 1][v][e] = sm;
         }
       }
       __syncthreads();
 
-      // ---- 3. face fluxes ---------------------------------------------------
-      for (int e = tid; e < (TX + 1) * TY; e += NT) {
-        const int f = e % (TX + 1), r = e / (TX + 1);
-        const int fi = i0 + f, jj = j0 + r;
-        if (fi <= B.ni && jj < B.nj) {
+      // ---- 3. face fluxes: i-faces then j-faces, one code path ------------
+      for (int e = tid; e < NFL; e += NT) {
+        int pL, st, sL, sR, fi, fj, d, face, t1;
+        bool valid;
+        if (e < NFX) {
+          const int f = e % (TX + 1), r = e / (TX + 1);
+          pL = (r + 2) * LX + f + 1;
+          st = 1;
+          sL = r * (TX + 2) + f;
+          sR = sL + 1;
+          fi = i0 + f;
+          fj = j0 + r;
+          d = 0;
+          face = fi == 0 ? 0 : (fi == B.ni ? 1 : -1);
+          t1 = fj;
+          valid = fi <= B.ni && fj < B.nj;
+        } else {
+          const int e2i = e - NFX;
+          const int c = e2i % TX, f = e2i / TX;
+          pL = (f + 1) * LX + c + 2;
+          st = LX;
+          sL = NSX + f * TX + c;
+          sR = sL + TX;
+          fi = i0 + c;
+          fj = j0 + f;
+          d = 1;
+          face = fj == 0 ? 2 : (fj == B.nj ? 3 : -1);
+          t1 = fi;
+          valid = fi < B.ni && fj <= B.nj;
+        }
+        if (valid) {
           double S[DIM], F[NV];
+          const long long fidx = pidx(B, fi, fj, k);
 #pragma unroll
-          for (int c = 0; c < DIM; ++c) S[c] = met[ML::S(0, c) * vs + pidx(B, fi, jj, k)];
-          const int face = fi == 0 ? 0 : (fi == B.ni ? 1 : -1);
-          if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, jj, k)) {
-            const double pw = face == 0 ? wall_pressure<DIM>(sq[NV - 1][r + 2][f + 2], sq[NV - 1][r + 2][f + 3])
-                                        : wall_pressure<DIM>(sq[NV - 1][r + 2][f + 1], sq[NV - 1][r + 2][f]);
-            wall_flux<DIM>(pw, S, F);
+          for (int c = 0; c < DIM; ++c) S[c] = met[ML::S(d, c) * vs + fidx];
+          if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, t1, k)) {
+            // p0 = cell next to the wall, p1 = the one after it
+            const int pin = (face & 1) ? pL : pL + st;
+            const int dir = (face & 1) ? -st : st;
+            wall_flux<DIM>(wall_pressure(sq[NV - 1][pin], sq[NV - 1][pin + dir]), S, F);
           } else {
             double L[NV], R[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-              L[v] = sq[v][r + 2][f + 1] + he * ssx[0][v][r][f];
-              R[v] = sq[v][r + 2][f + 2] - he * ssx[NS - 1][v][r][f + 1];
+              L[v] = sq[v][pL] + he * sl[0][v][sL];
+              R[v] = sq[v][pL + st] - he * sl[NS - 1][v][sR];
             }
-            roe_flux<DIM>(L, R, S, a.gas, a.efix, F);
+            roe_flux<DIM>(L, R, S, a.gas, a.efix, a.half_inv_efix, F);
           }
 #pragma unroll
-          for (int v = 0; v < NV; ++v) sfx[v][r][f] = F[v];
+          for (int v = 0; v < NV; ++v) fl[v][e] = F[v];
         }
       }
-      for (int e = tid; e < TX * (TY + 1); e += NT) {
-        const int c = e % TX, f = e / TX;
-        const int ii = i0 + c, fj = j0 + f;
-        if (ii < B.ni && fj <= B.nj) {
-          double S[DIM], F[NV];
-#pragma unroll
-          for (int cc = 0; cc < DIM; ++cc) S[cc] = met[ML::S(1, cc) * vs + pidx(B, ii, fj, k)];
-          const int face = fj == 0 ? 2 : (fj == B.nj ? 3 : -1);
-          if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, ii, k)) {
-            const double pw = face == 2 ? wall_pressure<DIM>(sq[NV - 1][f + 2][c + 2], sq[NV - 1][f + 3][c + 2])
-                                        : wall_pressure<DIM>(sq[NV - 1][f + 1][c + 2], sq[NV - 1][f][c + 2]);
-            wall_flux<DIM>(pw, S, F);
-          } else {
-            double L[NV], R[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-              L[v] = sq[v][f + 1][c + 2] + he * ssy[0][v][f][c];
-              R[v] = sq[v][f + 2][c + 2] - he * ssy[NS - 1][v][f + 1][c];
-            }
-            roe_flux<DIM>(L, R, S, a.gas, a.efix, F);
-          }
-#pragma unroll
-          for (int v = 0; v < NV; ++v) sfy[v][f][c] = F[v];
-        }
+      if constexpr (DIM == 3) {
+        if (own) zflux(k, fzhi);
       }
       __syncthreads();
 
@@ -287,10 +297,12 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
       if (own) {
         const long long ci = pidx(B, i, j, k);
         const double iv = met[ML::INVVOL * vs + ci];
+        const int ex = ty * (TX + 1) + tx;  // i-face on this cell's low side
+        const int ey = NFX + ty * TX + tx;  // j-face on this cell's low side
         double R[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          double div = (sfx[v][ty][tx + 1] - sfx[v][ty][tx]) + (sfy[v][ty + 1][tx] - sfy[v][ty][tx]);
+          double div = (fl[v][ex + 1] - fl[v][ex]) + (fl[v][ey + TX] - fl[v][ey]);
           if constexpr (DIM == 3) div += fzhi[v] - fzlo[v];
           R[v] = div * iv;
         }
@@ -299,10 +311,15 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) a.Rout[v * B.ncell_total + pc] = R[v];
         } else {
-          const double* q0 = a.q0 + B.origin;
           double w[NV], Q[NV], qnew[NV];
+          if (q0_is_qin) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) w[v] = q0[v * vs + ci];
+            for (int v = 0; v < NV; ++v) w[v] = sq[v][(ty + 2) * LX + tx + 2];
+          } else {
+            const double* q0 = a.q0 + B.origin;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) w[v] = q0[v * vs + ci];
+          }
           prim_to_cons<DIM>(w, a.gas, Q);
 #pragma unroll
           for (int v = 0; v < NV; ++v) Q[v] -= adt * R[v];
