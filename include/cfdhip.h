@@ -186,6 +186,47 @@ cfd_status cfd_set_variant(cfd_ctx* ctx, int variant);
 cfd_status cfd_profile(cfd_ctx* ctx, int enable);
 cfd_status cfd_kernel_time(cfd_ctx* ctx, double* total_ms, long long* launches);
 
+/* ---- adjoint (residual vector-Jacobian products) --------------------------
+ * Not in the paper: a hand-written reverse-mode derivative of the residual
+ * above (ghost fill, MUSCL with the symmetric limiters or none, Roe flux with
+ * Harten smoothing, wall override, divergence), so gradients of functionals of
+ * the solution with respect to the state, the node coordinates and the inflow
+ * states can be formed.  The context must be created with cfd_enable_adjoint
+ * before cfd_finalize (it reserves the extra workspace).  Cotangents use the
+ * same layouts as their primal values (packed conservative state, node
+ * layout, dim+2 values per inflow patch in patch-id order of the inflow
+ * patches).  Node gradients are implemented for 2D grids. */
+
+/* Reserve adjoint workspace (call before cfd_finalize). */
+cfd_status cfd_enable_adjoint(cfd_ctx* ctx, int enable);
+/* dev_Qbar = (dR/dQ)^T dev_Rbar at the current state; if not NULL,
+ * dev_Xbar = (dR/dX)^T dev_Rbar (nodes) and dev_BCbar = (dR/dtheta)^T dev_Rbar
+ * (inflow states).  Clears the metric/inflow accumulators first. */
+cfd_status cfd_residual_vjp(cfd_ctx* ctx, const double* dev_Rbar, double* dev_Qbar, double* dev_Xbar,
+                            double* dev_BCbar);
+/* Zero the accumulated node-metric and inflow cotangents. */
+cfd_status cfd_adjoint_reset(cfd_ctx* ctx);
+/* Reverse one Runge-Kutta step taken from the current state (the state at
+ * the start of that step, e.g. restored with cfd_load_state): on entry
+ * dev_Qbar holds dJ/dQ^{n+1}, on return dJ/dQ^n; the metric and inflow
+ * cotangents of the step accumulate.  Needs CFD_DT_FIXED and at most 4 stages. */
+cfd_status cfd_rk_step_vjp(cfd_ctx* ctx, double* dev_Qbar);
+/* J = sum over slip-wall faces of p_w |S| (integrated wall pressure) into
+ * dev_J[0]; dev_Qbar (nullable) = dJ/dQ; dJ/dS accumulates. */
+cfd_status cfd_objective_wall_pressure(cfd_ctx* ctx, double* dev_J, double* dev_Qbar);
+/* Node gradient (2D) and inflow-state gradient of everything accumulated since
+ * the last reset (both nullable). */
+cfd_status cfd_adjoint_result(cfd_ctx* ctx, double* dev_Xbar, double* dev_BCbar);
+/* dev_thetabar[dim+2] = (dQ/dtheta)^T sum over cells of dev_Qbar, for a
+ * uniform state Q = Q(theta) with primitive theta_host[dim+2]. */
+cfd_status cfd_uniform_state_vjp(cfd_ctx* ctx, const double* theta_host, const double* dev_Qbar,
+                                 double* dev_thetabar);
+/* Bit-exact copy of the internal solution (checkpoints): cfd_state_size
+ * bytes, device memory. */
+cfd_status cfd_state_size(cfd_ctx* ctx, size_t* bytes);
+cfd_status cfd_save_state(cfd_ctx* ctx, void* dev_dst);
+cfd_status cfd_load_state(cfd_ctx* ctx, const void* dev_src);
+
 enum {
   CFD_Q_NBLOCKS = 0, CFD_Q_NCELLS = 1, CFD_Q_NVAR = 2, CFD_Q_NVARIANTS = 3, CFD_Q_VARIANT = 4,
   CFD_Q_NTILES = 5, CFD_Q_NTRANSFERS = 6, CFD_Q_NPATCHES = 7, CFD_Q_NNODES = 8,

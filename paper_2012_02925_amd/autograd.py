@@ -1,0 +1,92 @@
+"""torch.autograd bindings of the hand-written adjoint.
+
+ResidualFn          R(Q) as a differentiable op: forward cfd_residual,
+                    backward cfd_residual_vjp.
+UnrolledWallPressure J(theta, X) = integrated wall pressure after n Runge-Kutta
+                    steps from the uniform state theta (inflow state, also the
+                    inflow boundary value) on nodes X.  Forward keeps a
+                    checkpoint (bit-exact copy of the solution) every `every`
+                    steps; backward replays each segment from its checkpoint,
+                    keeps the step-start states of that segment, and reverses
+                    the steps with cfd_rk_step_vjp (which recomputes the stage
+                    states of one step and sweeps its stages backwards).
+
+All arithmetic runs in the library's kernels; this module only sequences the
+calls and marshals tensors.
+"""
+import torch
+
+
+class ResidualFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, Q, solver):
+        solver.set_state(Q)
+        R = solver.residual()
+        ctx.solver = solver
+        ctx.save_for_backward(Q)
+        return R
+
+    @staticmethod
+    def backward(ctx, Rbar):
+        (Q,) = ctx.saved_tensors
+        s = ctx.solver
+        s.set_state(Q)
+        Qbar, _, _ = s.residual_vjp(Rbar.contiguous())
+        return Qbar, None
+
+
+def residual(solver, Q):
+    return ResidualFn.apply(Q, solver)
+
+
+def _uniform_prims(solver, theta):
+    th = theta.detach().to(device=solver.device, dtype=torch.float64)
+    return th.reshape(-1, 1).expand(solver.nvar, solver.ncells).contiguous()
+
+
+class UnrolledWallPressure(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, nodes, solver, nsteps, every, inflow_patch):
+        s = solver
+        s.set_nodes(nodes.detach())
+        th = [float(x) for x in theta.detach().cpu()]
+        s.set_bc_params(inflow_patch, th)
+        s.set_state_primitive(_uniform_prims(s, theta))
+        ckpts = []
+        for n in range(nsteps):
+            if n % every == 0:
+                ckpts.append((n, s.save_state()))
+            s.rk_step(1)
+        J, _ = s.objective_wall_pressure(with_grad=False)
+        ctx.solver, ctx.nsteps, ctx.every, ctx.th = s, nsteps, every, th
+        ctx.ckpts = ckpts
+        ctx.final = s.save_state()
+        ctx.theta_device = theta.device
+        ctx.nodes_shape = nodes.shape
+        return J.reshape(()).to(theta.device)
+
+    @staticmethod
+    def backward(ctx, Jbar):
+        s = ctx.solver
+        s.adjoint_reset()
+        s.load_state(ctx.final)
+        _, Qbar = s.objective_wall_pressure(with_grad=True)
+        Qbar = Qbar.contiguous()
+        for (start, buf) in reversed(ctx.ckpts):
+            end = min(start + ctx.every, ctx.nsteps)
+            s.load_state(buf)
+            states = [s.save_state()]
+            for _ in range(start, end - 1):
+                s.rk_step(1)
+                states.append(s.save_state())
+            for st in reversed(states):
+                s.load_state(st)
+                s.rk_step_vjp(Qbar)
+        Xbar, Tbar = s.adjoint_result(nodes=True, inflow=True)
+        theta_bar = s.uniform_state_vjp(ctx.th, Qbar) + Tbar[0]
+        jb = Jbar.to(s.device)
+        return (jb * theta_bar).to(ctx.theta_device), (jb * Xbar).reshape(ctx.nodes_shape), None, None, None, None
+
+
+def unrolled_wall_pressure(solver, theta, nodes, nsteps, every=10, inflow_patch=0):
+    return UnrolledWallPressure.apply(theta, nodes, solver, nsteps, every, inflow_patch)

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcfdhip.so")
-SOURCES = ["api.hip", "kernels.hip"]
+SOURCES = ["api.hip", "kernels.hip", "adjoint.hip"]
 ARCH = os.environ.get("CFDHIP_ARCH", "gfx950")
 
 FLAGS = [

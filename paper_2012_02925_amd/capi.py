@@ -66,6 +66,16 @@ SIGNATURES = {
     "cfd_profile": ([_P, _I], _I),
     "cfd_kernel_time": ([_P, _DP, ctypes.POINTER(ctypes.c_longlong)], _I),
     "cfd_query": ([_P, _I, ctypes.POINTER(ctypes.c_longlong)], _I),
+    "cfd_enable_adjoint": ([_P, _I], _I),
+    "cfd_residual_vjp": ([_P, _P, _P, _P, _P], _I),
+    "cfd_adjoint_reset": ([_P], _I),
+    "cfd_rk_step_vjp": ([_P, _P], _I),
+    "cfd_objective_wall_pressure": ([_P, _P, _P], _I),
+    "cfd_adjoint_result": ([_P, _P, _P], _I),
+    "cfd_uniform_state_vjp": ([_P, _DP, _P, _P], _I),
+    "cfd_state_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], _I),
+    "cfd_save_state": ([_P, _P], _I),
+    "cfd_load_state": ([_P, _P], _I),
 }
 
 _lib = None

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/cfdhip.h"
+#include "adjoint.h"
 #include "cfd_internal.h"
 #include "kernels.h"
 #include "stage_kernel.h"
@@ -67,7 +68,8 @@ struct cfd_ctx {
   std::vector<std::vector<TileDev>> tiles_batched, tiles_block;  // per variant
   std::vector<std::vector<int>> tile_begin;                      // per variant, per block (+1)
   std::vector<long long> export_off;
-  long long ncells = 0, nnodes = 0, max_cells = 0, max_padded = 0, max_pos = 0, padded_total = 0;
+  long long ncells = 0, nnodes = 0, max_cells = 0, max_padded = 0, max_pos = 0, padded_total = 0, max_faces = 0,
+            max_nodes = 0;
   long long state_doubles = 0, metric_doubles = 0, xbuf_doubles = 0;
   int ninflow = 0;
 
@@ -86,6 +88,19 @@ struct cfd_ctx {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   bool graph_valid = false;
+
+  // adjoint
+  bool adjoint = false;
+  long long facebar_doubles = 0;
+  size_t off_stD = 0, off_qbar = 0, off_facebar = 0, off_metricbar = 0, off_G = 0, off_T = 0, off_thetabar = 0,
+         off_part = 0, off_partoff = 0, off_vjpchunks = 0, off_objchunks = 0, off_inflowlist = 0, off_walllist = 0,
+         off_sumpart = 0, off_J = 0;
+  std::vector<ChunkDev> vjp_chunks, obj_chunks;      // ghost transposes / objective, grouped by donor face
+  std::vector<int> vjp_begin, obj_begin;             // per face (size 2*dim + 1)
+  std::vector<long long> part_off;
+  std::vector<int> inflow_list, wall_list;
+  long long part_doubles = 0;
+  static constexpr int SUM_PARTS = 1024;
 
   // timing
   bool profiling = false;
@@ -366,8 +381,9 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
 
   // --- block layout ---------------------------------------------------------
   c->blocks.resize(nb);
-  long long cursor = 0, mcursor = 0, packed = 0, node0 = 0;
+  long long cursor = 0, mcursor = 0, fcursor = 0, packed = 0, node0 = 0;
   const int nmet = dim * dim + 1;
+  const int nfb = (2 * nv + 3) * dim;
   c->max_cells = c->max_padded = c->max_pos = 0;
   c->padded_total = 0;
   c->export_off.assign(nb, 0);
@@ -388,6 +404,8 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     cursor = align_ll(cursor + 14 + (nv - 1) * B.vstride + padded, 16);
     B.morigin = mcursor + 14 + K;
     mcursor = align_ll(mcursor + 14 + (nmet - 1) * B.vstride + padded, 16);
+    B.forigin = fcursor + 14 + K;
+    fcursor = align_ll(fcursor + 14 + (nfb - 1) * B.vstride + padded, 16);
     B.packed = packed;
     const long long ncell = (long long)h.ni * h.nj * h.nk;
     packed += ncell;
@@ -403,6 +421,10 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     c->export_off[b] = c->padded_total;
     c->padded_total += pe * nv;
     c->max_pos = std::max(c->max_pos, (long long)(h.ni + 1) * (h.nj + 1) * (dim == 3 ? h.nk + 1 : 1));
+    c->max_nodes = c->max_pos;
+    long long nfaces = (long long)(h.ni + 1) * h.nj * h.nk + (long long)h.ni * (h.nj + 1) * h.nk;
+    if (dim == 3) nfaces += (long long)h.ni * h.nj * (h.nk + 1);
+    c->max_faces = std::max(c->max_faces, nfaces);
   }
   for (auto& B : c->blocks) {
     B.ncell_total = packed;
@@ -412,6 +434,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->nnodes = node0;
   c->state_doubles = cursor;
   c->metric_doubles = mcursor;
+  c->facebar_doubles = fcursor;
 
   // --- transfers, patches and ghost-fill chunks ------------------------------
   c->xfers.clear();
@@ -534,6 +557,54 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     c->off_tiles_batched[v] = take(c->tiles_batched[v].size() * sizeof(TileDev));
     c->off_tiles_block[v] = take(c->tiles_block[v].size() * sizeof(TileDev));
   }
+  if (c->adjoint) {
+    // ghost transposes grouped by donor face: transfers by their donor face,
+    // patches by their own face; one element per tangential position
+    const int nf = 2 * dim;
+    c->vjp_chunks.clear();
+    c->obj_chunks.clear();
+    c->vjp_begin.assign(nf + 1, 0);
+    c->obj_begin.assign(nf + 1, 0);
+    for (int f = 0; f < nf; ++f) {
+      c->vjp_begin[f] = (int)c->vjp_chunks.size();
+      for (size_t x = 0; x < c->xfers.size(); ++x)
+        if (c->xfers[x].dface == f) add_chunks(c->vjp_chunks, 0, (int)x, c->xfers[x].len0 * c->xfers[x].len1);
+      for (size_t p = 0; p < c->patches.size(); ++p)
+        if (c->patches[p].face == f) add_chunks(c->vjp_chunks, 1, (int)p, c->patches[p].len0 * c->patches[p].len1);
+      c->obj_begin[f] = (int)c->obj_chunks.size();
+      for (size_t p = 0; p < c->patches.size(); ++p)
+        if (c->patches[p].face == f && c->patches[p].kind == PK_SLIP_WALL)
+          add_chunks(c->obj_chunks, 1, (int)p, c->patches[p].len0 * c->patches[p].len1);
+    }
+    c->vjp_begin[nf] = (int)c->vjp_chunks.size();
+    c->obj_begin[nf] = (int)c->obj_chunks.size();
+    c->part_off.assign(c->patches.size(), 0);
+    c->inflow_list.clear();
+    c->wall_list.clear();
+    long long po = 0;
+    for (size_t p = 0; p < c->patches.size(); ++p) {
+      c->part_off[p] = po;
+      po += (long long)nv * c->patches[p].len0 * c->patches[p].len1;
+      if (c->patches[p].kind == PK_SUP_INFLOW) c->inflow_list.push_back((int)p);
+      if (c->patches[p].kind == PK_SLIP_WALL) c->wall_list.push_back((int)p);
+    }
+    c->part_doubles = std::max(po, 16LL);
+    c->off_stD = take(c->state_doubles * 8);
+    c->off_qbar = take(c->state_doubles * 8);
+    c->off_facebar = take(c->facebar_doubles * 8);
+    c->off_metricbar = take(c->metric_doubles * 8);
+    c->off_G = take((size_t)nv * c->ncells * 8);
+    c->off_T = take((size_t)nv * c->ncells * 8);
+    c->off_thetabar = take((size_t)std::max(c->ninflow, 1) * MAXV * 8);
+    c->off_part = take(c->part_doubles * 8);
+    c->off_partoff = take(c->part_off.size() * sizeof(long long));
+    c->off_vjpchunks = take(c->vjp_chunks.size() * sizeof(ChunkDev));
+    c->off_objchunks = take(c->obj_chunks.size() * sizeof(ChunkDev));
+    c->off_inflowlist = take(c->inflow_list.size() * sizeof(int));
+    c->off_walllist = take(c->wall_list.size() * sizeof(int));
+    c->off_sumpart = take((size_t)cfd_ctx::SUM_PARTS * MAXV * 8);
+    c->off_J = take(8);
+  }
   c->ws_bytes = off;
   c->finalized = true;
   if (ws_bytes) *ws_bytes = off;
@@ -582,6 +653,14 @@ extern "C" cfd_status cfd_bind_workspace(cfd_ctx* c, void* ptr, size_t bytes) {
   for (int v = 0; v < c->nvariants; ++v) {
     if ((s = upload(c, c->off_tiles_batched[v], c->tiles_batched[v])) != CFD_OK) return s;
     if ((s = upload(c, c->off_tiles_block[v], c->tiles_block[v])) != CFD_OK) return s;
+  }
+  if (c->adjoint) {
+    if ((s = upload(c, c->off_partoff, c->part_off)) != CFD_OK) return s;
+    if ((s = upload(c, c->off_vjpchunks, c->vjp_chunks)) != CFD_OK) return s;
+    if ((s = upload(c, c->off_objchunks, c->obj_chunks)) != CFD_OK) return s;
+    if ((s = upload(c, c->off_inflowlist, c->inflow_list)) != CFD_OK) return s;
+    if ((s = upload(c, c->off_walllist, c->wall_list)) != CFD_OK) return s;
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->off_stD, 0, c->off_G - c->off_stD, c->stream));
   }
   // nodes: [coord][concatenated nodes]
   std::vector<double> nodes((size_t)c->nnodes * c->dim);
@@ -1006,4 +1085,200 @@ extern "C" cfd_status cfd_query(cfd_ctx* c, int what, long long* value) {
     case CFD_Q_WORKSPACE_BYTES: *value = (long long)c->ws_bytes; return CFD_OK;
     default: return fail(c, CFD_ERR_ARG, "unknown query %d", what);
   }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+
+extern "C" cfd_status cfd_enable_adjoint(cfd_ctx* c, int enable) {
+  if (!c) return CFD_ERR_ARG;
+  if (c->finalized) return fail(c, CFD_ERR_STATE, "enable_adjoint after finalize");
+  c->adjoint = enable != 0;
+  return CFD_OK;
+}
+
+static VjpArgs vjp_args(cfd_ctx* c, const double* q, const double* Rb, double scale, double* out, double* acc) {
+  VjpArgs a{};
+  a.blocks = c->dptr<BlockDev>(c->off_blocks);
+  a.xfers = c->dptr<TransferDev>(c->off_xfers);
+  a.patches = c->dptr<PatchDev>(c->off_patches);
+  a.npatches = (int)c->patches.size();
+  a.q = q;
+  a.metric = c->metric();
+  a.nodes = c->dptr<double>(c->off_nodes);
+  a.Rb = Rb;
+  a.facebar = c->dptr<double>(c->off_facebar);
+  a.qbar = c->dptr<double>(c->off_qbar);
+  a.metricbar = c->dptr<double>(c->off_metricbar);
+  a.thetabar = c->dptr<double>(c->off_thetabar);
+  a.inflow_part = c->dptr<double>(c->off_part);
+  a.part_offset = c->dptr<long long>(c->off_partoff);
+  a.out = out;
+  a.acc = acc;
+  a.scale = scale;
+  a.gas = make_gas(c->cfg.gamma);
+  a.half_eps = 0.5 * c->cfg.muscl_eps;
+  a.kappa = c->cfg.muscl_kappa;
+  a.efix = c->cfg.efix;
+  a.half_inv_efix = c->cfg.efix > 0.0 ? 0.5 / c->cfg.efix : 0.0;
+  for (int v = 0; v < MAXV; ++v) a.e2[v] = c->cfg.lim_eps[v] * c->cfg.lim_eps[v];
+  return a;
+}
+
+static cfd_status need_adjoint(cfd_ctx* c) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!c->adjoint) return fail(c, CFD_ERR_STATE, "adjoint not enabled before finalize (cfd_enable_adjoint)");
+  if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
+  return CFD_OK;
+}
+
+// Residual VJP at state buffer q (ghosts filled): out = scale * (dR/dQ)^T Rb,
+// acc += the same; scale * dJ/dS, dJ/dOmega, dJ/dtheta accumulate.
+static cfd_status vjp_core(cfd_ctx* c, const double* q, const double* Rb, double scale, double* out, double* acc) {
+  const int nb = (int)c->blocks.size();
+  VjpArgs a = vjp_args(c, q, Rb, scale, out, acc);
+  hipStream_t s = c->stream;
+  HIP_TRY(c, launch_vjp_face(c->dim, c->cfg.limiter, a, c->max_faces, nb, s));
+  HIP_TRY(c, launch_vjp_cell(c->dim, c->cfg.limiter, a, c->max_padded, nb, s));
+  for (int f = 0; f < 2 * c->dim; ++f)
+    HIP_TRY(c, launch_vjp_ghost(c->dim, a, c->dptr<ChunkDev>(c->off_vjpchunks), c->vjp_begin[f],
+                                c->vjp_begin[f + 1] - c->vjp_begin[f], s));
+  HIP_TRY(c, launch_vjp_finalize(c->dim, a, c->max_cells, nb, s));
+  HIP_TRY(c, launch_vjp_inflow_reduce(c->dim, a, c->dptr<int>(c->off_inflowlist), (int)c->inflow_list.size(), s));
+  return CFD_OK;
+}
+
+static cfd_status copy_thetabar(cfd_ctx* c, double* dev_BCbar) {
+  if (!dev_BCbar || c->ninflow == 0) return CFD_OK;
+  HIP_TRY(c, hipMemcpy2DAsync(dev_BCbar, c->nvar * 8, c->dptr<double>(c->off_thetabar), MAXV * 8, c->nvar * 8,
+                              c->ninflow, hipMemcpyDeviceToDevice, c->stream));
+  return CFD_OK;
+}
+
+static cfd_status node_gradient(cfd_ctx* c, double* dev_Xbar) {
+  if (!dev_Xbar) return CFD_OK;
+  if (c->dim != 2) return fail(c, CFD_ERR_UNSUPPORTED, "node gradient is implemented for 2D grids");
+  VjpArgs a = vjp_args(c, c->stA(), nullptr, 1.0, nullptr, nullptr);
+  HIP_TRY(c, launch_node_vjp_2d(a, dev_Xbar, c->max_nodes, (int)c->blocks.size(), c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_adjoint_reset(cfd_ctx* c) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!c->adjoint) return fail(c, CFD_ERR_STATE, "adjoint not enabled");
+  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_metricbar, 0, c->metric_doubles * 8, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_thetabar, 0, (size_t)std::max(c->ninflow, 1) * MAXV * 8, c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_adjoint_result(cfd_ctx* c, double* dev_Xbar, double* dev_BCbar) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!c->adjoint) return fail(c, CFD_ERR_STATE, "adjoint not enabled");
+  if ((s = node_gradient(c, dev_Xbar)) != CFD_OK) return s;
+  return copy_thetabar(c, dev_BCbar);
+}
+
+extern "C" cfd_status cfd_residual_vjp(cfd_ctx* c, const double* dev_Rbar, double* dev_Qbar, double* dev_Xbar,
+                                       double* dev_BCbar) {
+  cfd_status s = need_adjoint(c);
+  if (s != CFD_OK) return s;
+  if (!dev_Rbar || !dev_Qbar) return CFD_ERR_ARG;
+  if (dev_Xbar && c->dim != 2) return fail(c, CFD_ERR_UNSUPPORTED, "node gradient is implemented for 2D grids");
+  if ((s = cfd_adjoint_reset(c)) != CFD_OK) return s;
+  if ((s = fill_ghosts(c, c->stA(), c->stream)) != CFD_OK) return s;
+  if ((s = vjp_core(c, c->stA(), dev_Rbar, 1.0, dev_Qbar, nullptr)) != CFD_OK) return s;
+  return cfd_adjoint_result(c, dev_Xbar, dev_BCbar);
+}
+
+extern "C" cfd_status cfd_rk_step_vjp(cfd_ctx* c, double* dev_Qbar) {
+  cfd_status s = need_adjoint(c);
+  if (s != CFD_OK) return s;
+  if (!dev_Qbar) return CFD_ERR_ARG;
+  if (c->cfg.dt_mode != CFD_DT_FIXED)
+    return fail(c, CFD_ERR_UNSUPPORTED, "the step adjoint needs a fixed time step (CFD_DT_FIXED)");
+  const int M = c->cfg.rk_stages;
+  if (M > 4) return fail(c, CFD_ERR_UNSUPPORTED, "the step adjoint keeps at most 4 stage states");
+  double* st[4] = {c->stA(), c->stB(), c->stC(), c->dptr<double>(c->off_stD)};
+  // recompute the stage states Q^(1..M-1) of this step from Q^(0) in A
+  for (int k = 1; k < M; ++k) {
+    if ((s = fill_ghosts(c, st[k - 1], c->stream)) != CFD_OK) return s;
+    StageArgs a = stage_args(c);
+    a.qin = st[k - 1];
+    a.q0 = st[0];
+    a.qout = st[k];
+    a.mode = MODE_STAGE;
+    a.alpha = 1.0 / (double)(M - k + 1);
+    a.dtmin = nullptr;
+    if ((s = launch_stage_all(c, a, c->stream, false)) != CFD_OK) return s;
+  }
+  if ((s = fill_ghosts(c, st[M - 1], c->stream)) != CFD_OK) return s;
+  // reverse sweep: acc (= dev_Qbar) collects dJ/dQ^(0); G is the cotangent of Q^(k)
+  const size_t bytes = (size_t)c->nvar * c->ncells * 8;
+  double* G = c->dptr<double>(c->off_G);
+  double* T = c->dptr<double>(c->off_T);
+  HIP_TRY(c, hipMemcpyAsync(G, dev_Qbar, bytes, hipMemcpyDeviceToDevice, c->stream));
+  const double dt = c->cfg.dt_fixed;
+  for (int k = M; k >= 1; --k) {
+    const double sc = -dt / (double)(M - k + 1);
+    if ((s = vjp_core(c, st[k - 1], G, sc, k > 1 ? T : nullptr, dev_Qbar)) != CFD_OK) return s;
+    std::swap(G, T);
+  }
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_objective_wall_pressure(cfd_ctx* c, double* dev_J, double* dev_Qbar) {
+  cfd_status s = need_adjoint(c);
+  if (s != CFD_OK) return s;
+  if (!dev_J) return CFD_ERR_ARG;
+  VjpArgs a = vjp_args(c, c->stA(), nullptr, 1.0, dev_Qbar, nullptr);
+  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_qbar, 0, c->state_doubles * 8, c->stream));
+  for (int f = 0; f < 2 * c->dim; ++f)
+    HIP_TRY(c, launch_objective(c->dim, a, c->dptr<ChunkDev>(c->off_objchunks), c->obj_begin[f],
+                                c->obj_begin[f + 1] - c->obj_begin[f], c->stream));
+  HIP_TRY(c, launch_objective_sum(a, c->dptr<int>(c->off_walllist), (int)c->wall_list.size(), dev_J, c->stream));
+  if (dev_Qbar) HIP_TRY(c, launch_vjp_finalize(c->dim, a, c->max_cells, (int)c->blocks.size(), c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_uniform_state_vjp(cfd_ctx* c, const double* theta_host, const double* dev_Qbar,
+                                            double* dev_thetabar) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!c->adjoint) return fail(c, CFD_ERR_STATE, "adjoint not enabled");
+  if (!theta_host || !dev_Qbar || !dev_thetabar) return CFD_ERR_ARG;
+  double th[5] = {0, 0, 0, 0, 0};
+  for (int v = 0; v < c->nvar; ++v) th[v] = theta_host[v];
+  const int parts = (int)std::min<long long>(cfd_ctx::SUM_PARTS, std::max<long long>(1, c->ncells / 256));
+  HIP_TRY(c, launch_uniform_state_vjp(c->dim, dev_Qbar, c->ncells, c->dptr<double>(c->off_sumpart), parts,
+                                      dev_thetabar, make_gas(c->cfg.gamma), th, c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_state_size(cfd_ctx* c, size_t* bytes) {
+  cfd_status s = need(c, true, false);
+  if (s != CFD_OK) return s;
+  if (!bytes) return CFD_ERR_ARG;
+  *bytes = (size_t)c->state_doubles * 8;
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_save_state(cfd_ctx* c, void* dev_dst) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!dev_dst) return CFD_ERR_ARG;
+  HIP_TRY(c, hipMemcpyAsync(dev_dst, c->stA(), (size_t)c->state_doubles * 8, hipMemcpyDeviceToDevice, c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_load_state(cfd_ctx* c, const void* dev_src) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!dev_src) return CFD_ERR_ARG;
+  HIP_TRY(c, hipMemcpyAsync(c->stA(), dev_src, (size_t)c->state_doubles * 8, hipMemcpyDeviceToDevice, c->stream));
+  c->have_state = true;
+  c->dt_valid = false;
+  return ensure_dt(c);
 }

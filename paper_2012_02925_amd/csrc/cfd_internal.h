@@ -23,6 +23,7 @@ struct BlockDev {
   long long vstride;       // doubles between two padded arrays of this block
   long long origin;        // offset of interior (0,0,0) of array 0 within a state buffer
   long long morigin;       // offset of interior (0,0,0) of metric array 0 within the metric buffer
+  long long forigin;       // offset of interior (0,0,0) of face-scratch array 0 (adjoint)
   long long packed;        // first cell of the block in the packed [var][cell] layout
   long long node0;         // first node of the block in the concatenated node layout
   long long ncell_total;   // cells of all blocks (stride between packed variables)
@@ -81,9 +82,9 @@ __host__ __device__ inline void orient_map(int orient, int r1, int r2, int dlen0
   d2 = (orient & 2) ? (dlen1 - 1 - s2) : s2;
 }
 
-// Cell (i,j,k) of layer `layer` (0 = adjacent to the face, counted inward for
-// interior layers) at tangential offset (t1, t2) from the range start
-// (lo0, lo1).  ghost = true counts outward (layer 0 = first ghost layer).
+// Cell (i,j,k) of layer `layer` of a face (0 = adjacent to the face, counted
+// inward for interior layers; ghost = true counts outward, layer 0 = first
+// ghost layer) at tangential cell coordinates (t1, t2).
 __host__ __device__ inline void face_cell(const BlockDev& b, int dim, int face, int layer, bool ghost,
                                           int t1, int t2, int& i, int& j, int& k) {
   int axis = face >> 1;

@@ -53,15 +53,19 @@ class Solver:
         self.workspace = None
         self.block_shapes = []
         self.patch_ids = []
+        self.patch_kinds = []
 
     # -- construction ------------------------------------------------------
     @classmethod
-    def from_case(cls, case, device="cuda", state=True):
+    def from_case(cls, case, device="cuda", state=True, adjoint=False):
         s = cls(case.dim, case.scheme, device)
+        if adjoint:
+            s.enable_adjoint()
         for b in case.blocks:
             s.add_block(b.ni, b.nj, b.nk, b.nodes)
         for p in case.bcs:
             s.patch_ids.append(s.set_bc(p.block, p.face, p.lo, p.hi, p.kind, p.params))
+            s.patch_kinds.append(p.kind)
         for c in case.conns:
             s.connect(c.block_a, c.face_a, c.lo_a, c.hi_a, c.block_b, c.face_b, c.lo_b, c.hi_b, c.orient)
         s.finalize_and_bind()
@@ -183,6 +187,77 @@ class Solver:
         n = ctypes.c_longlong()
         self._check(self.lib.cfd_kernel_time(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    # -- adjoint -------------------------------------------------------------
+    def enable_adjoint(self, enable=True):
+        self._check(self.lib.cfd_enable_adjoint(self.ctx, 1 if enable else 0))
+
+    def _zeros(self, n):
+        return torch.zeros(n, dtype=F64, device=self.device)
+
+    def nnodes(self):
+        return self.query("nnodes")
+
+    def residual_vjp(self, Rbar, nodes=False, inflow=False):
+        Rbar = Rbar.to(device=self.device, dtype=F64).contiguous()
+        Qbar = torch.empty((self.nvar, self.ncells), dtype=F64, device=self.device)
+        Xbar = torch.empty((self.dim, self.nnodes()), dtype=F64, device=self.device) if nodes else None
+        Tbar = torch.empty((max(self.ninflow, 1), self.nvar), dtype=F64, device=self.device) if inflow else None
+        self._check(self.lib.cfd_residual_vjp(self.ctx, dptr(Rbar), dptr(Qbar), None if Xbar is None else dptr(Xbar),
+                                              None if Tbar is None else dptr(Tbar)))
+        return Qbar, Xbar, Tbar
+
+    @property
+    def ninflow(self):
+        return sum(1 for k in self.patch_kinds if k == "sup_inflow")
+
+    def adjoint_reset(self):
+        self._check(self.lib.cfd_adjoint_reset(self.ctx))
+
+    def rk_step_vjp(self, Qbar):
+        """In place: Qbar holds dJ/dQ^{n+1} on entry and dJ/dQ^n on return."""
+        assert Qbar.is_contiguous() and Qbar.dtype == F64
+        self._check(self.lib.cfd_rk_step_vjp(self.ctx, dptr(Qbar)))
+        return Qbar
+
+    def objective_wall_pressure(self, with_grad=True):
+        J = torch.empty(1, dtype=F64, device=self.device)
+        Qbar = torch.empty((self.nvar, self.ncells), dtype=F64, device=self.device) if with_grad else None
+        self._check(self.lib.cfd_objective_wall_pressure(self.ctx, dptr(J), None if Qbar is None else dptr(Qbar)))
+        return J, Qbar
+
+    def adjoint_result(self, nodes=True, inflow=True):
+        Xbar = torch.empty((self.dim, self.nnodes()), dtype=F64, device=self.device) if nodes else None
+        Tbar = torch.empty((max(self.ninflow, 1), self.nvar), dtype=F64, device=self.device) if inflow else None
+        self._check(self.lib.cfd_adjoint_result(self.ctx, None if Xbar is None else dptr(Xbar),
+                                                None if Tbar is None else dptr(Tbar)))
+        return Xbar, Tbar
+
+    def uniform_state_vjp(self, theta, Qbar):
+        th = (ctypes.c_double * 5)(*([float(x) for x in theta] + [0.0] * (5 - len(theta))))
+        out = torch.empty(self.nvar, dtype=F64, device=self.device)
+        self._check(self.lib.cfd_uniform_state_vjp(self.ctx, ctypes.cast(th, capi._DP), dptr(Qbar.contiguous()),
+                                                   dptr(out)))
+        return out
+
+    def state_bytes(self):
+        n = ctypes.c_size_t()
+        self._check(self.lib.cfd_state_size(self.ctx, ctypes.byref(n)))
+        return n.value
+
+    def save_state(self, buf=None):
+        if buf is None:
+            buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.cfd_save_state(self.ctx, dptr(buf)))
+        return buf
+
+    def load_state(self, buf):
+        self._check(self.lib.cfd_load_state(self.ctx, dptr(buf)))
+
+    def pack_nodes(self, node_arrays):
+        """Per-block node arrays (dim, ...) -> concatenated (dim, nnodes) device tensor."""
+        flat = [torch.as_tensor(np.asarray(a), dtype=F64).reshape(self.dim, -1) for a in node_arrays]
+        return torch.cat(flat, dim=1).to(self.device).contiguous()
 
     def query(self, what):
         v = ctypes.c_longlong()

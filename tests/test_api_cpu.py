@@ -1,0 +1,195 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point the header declares, and its host-side planning validates topology."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cfdhip.h")
+
+
+def _lib():
+    from paper_2012_02925_amd import capi
+    if not os.path.exists(capi.LIB_PATH):
+        from paper_2012_02925_amd import build
+        build.build()
+    return capi, capi.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_and_library_exports_every_entry_point():
+    capi, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 30
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in capi.SIGNATURES, "binding missing for " + n
+
+
+def _cfg(capi, dim=2, **kw):
+    c = capi.CfdConfig()
+    c.dim = dim
+    c.gamma = 1.4
+    c.limiter = 1
+    c.muscl_eps = 1.0
+    c.muscl_kappa = -1.0
+    c.efix = 0.1
+    c.rk_stages = 4
+    c.dt_mode = 0
+    c.cfl = 0.5
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def _ctx(capi, lib, **kw):
+    ctx = ctypes.c_void_p()
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, **kw)), None, ctypes.byref(ctx)) == 0
+    return ctx
+
+
+def _add(capi, lib, ctx, ni, nj, nk=1, dim=2):
+    if dim == 2:
+        X = synth.cartesian_nodes_2d(ni, nj)
+    else:
+        X = synth.jittered_periodic_nodes_3d(ni, nj, nk, seed=0)
+    X = np.ascontiguousarray(X)
+    bid = ctypes.c_int()
+    st = lib.cfd_add_block(ctx, ni, nj, nk, X.ctypes.data_as(capi._DP), ctypes.byref(bid))
+    return st, bid.value
+
+
+def _periodic(capi, lib, ctx, b, ni, nj):
+    assert lib.cfd_connect(ctx, b, 0, capi.int2([0]), capi.int2([nj]), b, 1, capi.int2([0]), capi.int2([nj]), 0) == 0
+    assert lib.cfd_connect(ctx, b, 2, capi.int2([0]), capi.int2([ni]), b, 3, capi.int2([0]), capi.int2([ni]), 0) == 0
+
+
+def test_config_validation():
+    capi, lib = _lib()
+    ctx = ctypes.c_void_p()
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, dim=4)), None, ctypes.byref(ctx)) == -1
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, gamma=1.0)), None, ctypes.byref(ctx)) == -1
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, rk_stages=0)), None, ctypes.byref(ctx)) == -1
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, cfl=0.0)), None, ctypes.byref(ctx)) == -1
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, limiter=7)), None, ctypes.byref(ctx)) == -1
+
+
+def test_planning_and_workspace_size():
+    capi, lib = _lib()
+    ctx = _ctx(capi, lib)
+    st, b = _add(capi, lib, ctx, 64, 48)
+    assert st == 0 and b == 0
+    _periodic(capi, lib, ctx, 0, 64, 48)
+    n = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == 0
+    assert n.value > 3 * 4 * 64 * 48 * 8
+    v = ctypes.c_longlong()
+    assert lib.cfd_query(ctx, capi.Q["ncells"], ctypes.byref(v)) == 0 and v.value == 64 * 48
+    assert lib.cfd_query(ctx, capi.Q["ntransfers"], ctypes.byref(v)) == 0 and v.value == 4
+    # 4 transfers x 2 layers x face length x 4 variables
+    assert lib.cfd_query(ctx, capi.Q["exchange_doubles"], ctypes.byref(v)) == 0
+    assert v.value == 4 * 2 * (48 + 48 + 64 + 64)
+    lib.cfd_destroy(ctx)
+
+
+def test_empty_context_cannot_finalize():
+    capi, lib = _lib()
+    ctx = _ctx(capi, lib)
+    n = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == -2
+    assert b"no blocks" in lib.cfd_last_error(ctx)
+    lib.cfd_destroy(ctx)
+
+
+def test_block_extent_and_range_errors():
+    capi, lib = _lib()
+    ctx = _ctx(capi, lib)
+    assert _add(capi, lib, ctx, 1, 8)[0] == -1  # fewer than two cells
+    assert _add(capi, lib, ctx, 8, 8)[0] == 0
+    # range outside the face, bad face, bad kind
+    assert lib.cfd_set_bc(ctx, 0, 0, capi.int2([0]), capi.int2([9]), 3, None, None) == -1
+    assert lib.cfd_set_bc(ctx, 0, 5, capi.int2([0]), capi.int2([8]), 3, None, None) == -1
+    assert lib.cfd_set_bc(ctx, 0, 0, capi.int2([0]), capi.int2([8]), 9, None, None) == -1
+    # inflow needs positive density and pressure
+    bad = (ctypes.c_double * 5)(-1.0, 1.0, 0.0, 1.0, 0.0)
+    assert lib.cfd_set_bc(ctx, 0, 0, capi.int2([0]), capi.int2([8]), 2, ctypes.cast(bad, capi._DP), None) == -6
+    lib.cfd_destroy(ctx)
+
+
+def test_topology_errors():
+    capi, lib = _lib()
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    _add(capi, lib, ctx, 8, 5)
+    # extents differ (6 vs 5)
+    assert lib.cfd_connect(ctx, 0, 1, capi.int2([0]), capi.int2([6]), 1, 0, capi.int2([0]), capi.int2([5]), 0) == -3
+    lib.cfd_destroy(ctx)
+    # a face without boundary condition
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    assert lib.cfd_connect(ctx, 0, 0, capi.int2([0]), capi.int2([6]), 0, 1, capi.int2([0]), capi.int2([6]), 0) == 0
+    n = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == -3
+    assert b"without a boundary condition" in lib.cfd_last_error(ctx)
+    lib.cfd_destroy(ctx)
+    # overlapping definitions on one face
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    _periodic(capi, lib, ctx, 0, 8, 6)
+    assert lib.cfd_set_bc(ctx, 0, 2, capi.int2([2]), capi.int2([5]), 3, None, None) == 0
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == -3
+    assert b"overlapping" in lib.cfd_last_error(ctx)
+    lib.cfd_destroy(ctx)
+
+
+def test_calls_out_of_order():
+    capi, lib = _lib()
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    _periodic(capi, lib, ctx, 0, 8, 6)
+    buf = ctypes.c_void_p(4096)
+    assert lib.cfd_residual(ctx, buf) == -2          # not finalized
+    n = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == 0
+    assert lib.cfd_rk_step(ctx, 1, None) == -2        # no workspace
+    assert _add(capi, lib, ctx, 8, 8)[0] == -2         # after finalize
+    assert lib.cfd_enable_adjoint(ctx, 1) == -2       # after finalize
+    # binding without a device reports a HIP error on this host
+    assert lib.cfd_bind_workspace(ctx, ctypes.c_void_p(4096), n.value) == -5
+    lib.cfd_destroy(ctx)
+
+
+def test_tile_lists_cover_every_cell_once():
+    """Planning view: the tile count per variant covers the block exactly."""
+    capi, lib = _lib()
+    ctx = _ctx(capi, lib, dim=3)
+    st, _ = _add(capi, lib, ctx, 40, 36, 34, dim=3)
+    assert st == 0
+    for a, (n1, n2) in enumerate([(36, 34), (40, 34), (40, 36)]):
+        assert lib.cfd_connect(ctx, 0, 2 * a, capi.int2([0, 0]), capi.int2([n1, n2]), 0, 2 * a + 1,
+                               capi.int2([0, 0]), capi.int2([n1, n2]), 0) == 0
+    n = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == 0
+    v = ctypes.c_longlong()
+    nvar = ctypes.c_longlong()
+    lib.cfd_query(ctx, capi.Q["nvariants"], ctypes.byref(nvar))
+    import math
+    for var in range(nvar.value):
+        assert lib.cfd_set_variant(ctx, var) == 0
+        lib.cfd_query(ctx, capi.Q["tile_x"], ctypes.byref(v))
+        tx = v.value
+        lib.cfd_query(ctx, capi.Q["tile_y"], ctypes.byref(v))
+        ty = v.value
+        lib.cfd_query(ctx, capi.Q["ntiles"], ctypes.byref(v))
+        assert v.value >= math.ceil(40 / tx) * math.ceil(36 / ty)
+    lib.cfd_destroy(ctx)

@@ -1,0 +1,209 @@
+"""GPU adjoint: the hand-written residual VJP and the checkpointed unrolled
+gradient against the oracle's automatic differentiation and against central
+finite differences of the HIP forward path."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import gas
+
+pytestmark = pytest.mark.gpu
+
+VJP_TOL = 1e-10  # normwise: max|d| <= tol * max|ref| per output and variable
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(case):
+    from paper_2012_02925_amd.solver import Solver
+    return Solver.from_case(case, device="cuda:0", adjoint=True)
+
+
+def _ramp(ni=40, nj=26, lim="vanalbada", eps=1e-2, seed=0, dt=None):
+    c = synth.compression_ramp(ni, nj, limiter=lim, lim_eps=[eps, eps, eps, eps / 1.4], dt_fixed=dt)
+    rng = np.random.default_rng(seed)
+    c.prims[0] = c.prims[0] * (1 + 0.03 * rng.standard_normal(c.prims[0].shape))
+    return c
+
+
+def _oracle_vjp(case, Rbar_packed):
+    P = oracle.Problem(case, requires_grad=True)
+    Q = [q.detach().requires_grad_(True) for q in P.initial_state()]
+    R = P.residual(Q)
+    Rflat = torch.cat([r.reshape(case.nvar, -1) for r in R], dim=1)
+    leaves = Q + P.nodes + P.bc_params
+    g = torch.autograd.grad((Rflat * Rbar_packed).sum(), leaves, allow_unused=True)
+    nb = len(Q)
+    Qbar = torch.cat([x.reshape(case.nvar, -1) for x in g[:nb]], dim=1)
+    Xbar = torch.cat([x.reshape(case.dim, -1) for x in g[nb:2 * nb]], dim=1)
+    Tbar = g[2 * nb:]
+    return Qbar, Xbar, Tbar
+
+
+def _close(a, b, tol, what):
+    a = a.detach().cpu()
+    b = b.detach().cpu()
+    err = (a - b).abs().max().item()
+    ref = b.abs().max().item()
+    _say("  %s: max err %.3e, max ref %.3e, rel %.3e" % (what, err, ref, err / max(ref, 1e-300)))
+    assert err <= tol * ref, (what, err, ref)
+
+
+def _conservative_from_prims(case):
+    P = oracle.Problem(case)
+    return torch.cat([Q.reshape(case.nvar, -1) for Q in P.initial_state()], dim=1)
+
+
+@pytest.mark.parametrize("lim", ["vanalbada", "vanleer", "none"])
+def test_residual_vjp_matches_oracle_ramp(lim):
+    _say("case: ramp 40x26 residual VJP", lim)
+    case = _ramp(lim=lim)
+    s = _solver(case)
+    s.set_state(_conservative_from_prims(case).to("cuda:0"))
+    rng = np.random.default_rng(1)
+    Rbar = torch.tensor(rng.standard_normal((case.nvar, case.ncells)))
+    Qb, Xb, Tb = s.residual_vjp(Rbar.to("cuda:0"), nodes=True, inflow=True)
+    Qr, Xr, Tr = _oracle_vjp(case, Rbar)
+    for v in range(case.nvar):
+        _close(Qb[v], Qr[v], VJP_TOL, "Qbar[%d]" % v)
+    for c in range(2):
+        _close(Xb[c], Xr[c], VJP_TOL, "Xbar[%d]" % c)
+    _close(Tb[0], Tr[0], VJP_TOL, "inflow bar")
+
+
+def test_residual_vjp_matches_oracle_multiblock():
+    _say("case: patchwork 3x2 residual VJP")
+    case = synth.patchwork(seed=5, nbx=3, nby=2, side_lo=6, side_hi=20, h=1.0 / 40, limiter="vanalbada")
+    case.scheme.lim_eps = [1e-2, 1e-2, 1e-2, 1e-2 / 1.4]
+    s = _solver(case)
+    s.set_state(_conservative_from_prims(case).to("cuda:0"))
+    rng = np.random.default_rng(2)
+    Rbar = torch.tensor(rng.standard_normal((case.nvar, case.ncells)))
+    Qb, Xb, _ = s.residual_vjp(Rbar.to("cuda:0"), nodes=True)
+    Qr, Xr, _ = _oracle_vjp(case, Rbar)
+    for v in range(case.nvar):
+        _close(Qb[v], Qr[v], VJP_TOL, "Qbar[%d]" % v)
+    for c in range(2):
+        _close(Xb[c], Xr[c], VJP_TOL, "Xbar[%d]" % c)
+
+
+def test_residual_vjp_reversed_connection():
+    _say("case: reversed 2-block connection residual VJP")
+    base = synth.jittered_periodic_square(20, 14, seed=8, limiter="vanleer")
+    sp = synth.split_block_case(base, [9], [])
+    A, B = sp.blocks
+    Bn = synth.Block(B.ni, B.nj, 1, B.nodes[:, ::-1, ::-1].copy())
+    nj = A.nj
+    conns = [synth.Connection(0, synth.IMAX, [0], [nj], 1, synth.IMAX, [0], [nj], 1),
+             synth.Connection(0, synth.IMIN, [0], [nj], 1, synth.IMIN, [0], [nj], 1),
+             synth.Connection(0, synth.JMIN, [0], [A.ni], 0, synth.JMAX, [0], [A.ni], 0),
+             synth.Connection(1, synth.JMIN, [0], [B.ni], 1, synth.JMAX, [0], [B.ni], 0)]
+    case = synth.Case("rev", 2, [A, Bn], [], conns, [sp.prims[0], sp.prims[1][:, ::-1, ::-1].copy()],
+                      base.scheme, 1)
+    s = _solver(case)
+    s.set_state(_conservative_from_prims(case).to("cuda:0"))
+    rng = np.random.default_rng(3)
+    Rbar = torch.tensor(rng.standard_normal((case.nvar, case.ncells)))
+    Qb, Xb, _ = s.residual_vjp(Rbar.to("cuda:0"), nodes=True)
+    Qr, Xr, _ = _oracle_vjp(case, Rbar)
+    for v in range(case.nvar):
+        _close(Qb[v], Qr[v], VJP_TOL, "Qbar[%d]" % v)
+    _close(Xb, Xr, VJP_TOL, "Xbar")
+
+
+def test_residual_vjp_dot_product_with_gpu_fd():
+    """<Qbar, v> against central differences of the HIP residual itself."""
+    case = _ramp(64, 40)
+    s = _solver(case)
+    Q0 = _conservative_from_prims(case).to("cuda:0")
+    rng = np.random.default_rng(4)
+    Rbar = torch.tensor(rng.standard_normal((case.nvar, case.ncells))).to("cuda:0")
+    s.set_state(Q0)
+    Qb, _, _ = s.residual_vjp(Rbar)
+    h = 1e-7
+    for trial in range(3):
+        v = torch.tensor(rng.standard_normal(Q0.shape)).to("cuda:0") * Q0.abs().amax(dim=1, keepdim=True)
+        s.set_state(Q0 + h * v)
+        Rp = s.residual().clone()
+        s.set_state(Q0 - h * v)
+        Rm = s.residual().clone()
+        fd = ((Rp - Rm) * Rbar).sum().item() / (2 * h)
+        ad = (Qb * v).sum().item()
+        _say("  trial", trial, fd, ad)
+        assert abs(fd - ad) <= 1e-6 * abs(fd)
+
+
+def test_rk_step_vjp_matches_oracle():
+    _say("case: ramp 30x20, one RK step VJP")
+    case = _ramp(30, 20, dt=2e-3)
+    s = _solver(case)
+    s.set_state(_conservative_from_prims(case).to("cuda:0"))
+    rng = np.random.default_rng(5)
+    Gbar = torch.tensor(rng.standard_normal((case.nvar, case.ncells)))
+    s.adjoint_reset()
+    Qb = Gbar.clone().to("cuda:0").contiguous()
+    s.rk_step_vjp(Qb)
+    Xb, Tb = s.adjoint_result()
+    # oracle
+    P = oracle.Problem(case, requires_grad=True)
+    Q = [q.detach().requires_grad_(True) for q in P.initial_state()]
+    met = P.metrics()
+    Q1, _ = P.rk_step(Q, met)
+    g = torch.autograd.grad((Q1[0].reshape(case.nvar, -1) * Gbar).sum(), [Q[0], P.nodes[0], P.bc_params[0]])
+    _close(Qb, g[0].reshape(case.nvar, -1), VJP_TOL, "Qbar")
+    _close(Xb, g[1].reshape(2, -1), VJP_TOL, "Xbar")
+    _close(Tb[0], g[2], VJP_TOL, "inflow bar")
+
+
+def _oracle_unrolled_grad(case, steps):
+    theta0 = torch.tensor(case.meta["inflow"])
+    th = theta0.clone().requires_grad_(True)
+    P = oracle.Problem(case, requires_grad=True)
+    P.bc_params[0] = th
+    met = P.metrics()
+    q = th.reshape(-1, 1, 1).expand(case.prims[0].shape)
+    Q = [gas.cons_from_prim(q, P.gamma)]
+    for _ in range(steps):
+        Q, _ = P.rk_step(Q, met)
+    J = P.wall_pressure_integral(Q, met)
+    gT, gX = torch.autograd.grad(J, [th, P.nodes[0]])
+    return J.item(), gT, gX
+
+
+def test_unrolled_gradient_matches_oracle():
+    from paper_2012_02925_amd.autograd import unrolled_wall_pressure
+    _say("case: ramp 36x24, 12 steps, checkpoints every 5")
+    case = _ramp(36, 24, dt=2e-3)
+    steps = 12
+    Jr, gTr, gXr = _oracle_unrolled_grad(case, steps)
+    s = _solver(case)
+    theta = torch.tensor(case.meta["inflow"], requires_grad=True)
+    nodes = torch.tensor(case.blocks[0].nodes).reshape(2, -1).to("cuda:0").requires_grad_(True)
+    J = unrolled_wall_pressure(s, theta, nodes, steps, every=5)
+    J.backward()
+    _say("  J gpu %.15e oracle %.15e" % (J.item(), Jr))
+    assert abs(J.item() - Jr) <= 1e-12 * abs(Jr)
+    _close(theta.grad, gTr, VJP_TOL, "dJ/dtheta")
+    _close(nodes.grad, gXr.reshape(2, -1), VJP_TOL, "dJ/dX")
+
+
+def test_checkpoint_interval_does_not_change_gradient():
+    from paper_2012_02925_amd.autograd import unrolled_wall_pressure
+    case = _ramp(30, 20, dt=2e-3)
+    grads = []
+    for every in (1, 4, 10):
+        s = _solver(case)
+        theta = torch.tensor(case.meta["inflow"], requires_grad=True)
+        nodes = torch.tensor(case.blocks[0].nodes).reshape(2, -1).to("cuda:0").requires_grad_(True)
+        J = unrolled_wall_pressure(s, theta, nodes, 10, every=every)
+        J.backward()
+        grads.append((theta.grad.clone(), nodes.grad.clone().cpu()))
+    for g in grads[1:]:
+        assert torch.equal(g[0], grads[0][0]) and torch.equal(g[1], grads[0][1])
