@@ -96,6 +96,92 @@ def cpu_baseline(workload, target_s=12.0):
             "kind": "oracle", "sample": "%s, %d RK steps in %.1f s" % (sample, steps, el)}
 
 
+def bench_batching(steps=20, warmup=2):
+    """64-block patchwork (block sides uniform in [64, 512], all faces
+    connected): one launch per block per phase vs. batched launches inside a
+    captured hipGraph.  Same kernels, same tiles, bitwise-identical results."""
+    import torch
+
+    import synth
+    from paper_2012_02925_amd.solver import Solver
+
+    case = synth.patchwork(seed=0)
+    out = {"workload": case.name, "blocks": len(case.blocks), "cells": case.ncells}
+    results = {}
+    for mode, graph in (("per_block", False), ("batched", True)):
+        s = Solver.from_case(case, device="cuda:0")
+        s.set_exec(mode, graph)
+        s.rk_step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.rk_step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        results[mode] = case.ncells * case.scheme.rk_stages * steps / el
+        out[mode + "_ms_per_step"] = el * 1e3 / steps
+        s.close()
+    out["per_block_value"] = results["per_block"]
+    out["batched_graph_value"] = results["batched"]
+    out["speedup"] = results["batched"] / results["per_block"]
+    out["unit"] = "cell-updates/s per RK stage"
+    return out
+
+
+def bench_adjoint(n=512, steps=50, every=10):
+    """2D ramp n x n, van Albada (eps 1e-2), Roe, RK4 with the CFL step of the
+    initial state held fixed; objective = integrated wall pressure after
+    `steps` steps.  Forward: the unrolled steps with checkpoints; backward:
+    segment replay + reverse steps with the hand-written VJP."""
+    import torch
+
+    import synth
+    from paper_2012_02925_amd.autograd import unrolled_wall_pressure
+    from paper_2012_02925_amd.solver import Solver
+
+    probe = Solver.from_case(synth.compression_ramp(n, n, limiter="vanalbada"), device="cuda:0")
+    dt = probe.time_step().item()
+    probe.close()
+    eps = 1e-2
+    case = synth.compression_ramp(n, n, limiter="vanalbada", lim_eps=[eps, eps, eps, eps / 1.4], dt_fixed=dt)
+    s = Solver.from_case(case, device="cuda:0", adjoint=True)
+    theta = torch.tensor(case.meta["inflow"], requires_grad=True)
+    nodes = torch.tensor(case.blocks[0].nodes).reshape(2, -1).to("cuda:0").requires_grad_(True)
+    # warm-up pass (graph capture, allocator)
+    J = unrolled_wall_pressure(s, theta, nodes, 4, every)
+    J.backward()
+    theta.grad = None
+    nodes.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = unrolled_wall_pressure(s, theta, nodes, steps, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    # one residual vs one residual VJP
+    Rb = torch.ones((s.nvar, s.ncells), dtype=torch.float64, device="cuda:0")
+    s.residual()
+    s.residual_vjp(Rb)
+    torch.cuda.synchronize()
+    reps = 20
+    a0 = time.perf_counter()
+    for _ in range(reps):
+        s.residual()
+    torch.cuda.synchronize()
+    a1 = time.perf_counter()
+    for _ in range(reps):
+        s.residual_vjp(Rb)
+    torch.cuda.synchronize()
+    a2 = time.perf_counter()
+    fwd, bwd = t1 - t0, t2 - t1
+    return {"workload": "compression_ramp_%dx%d adjoint, %d steps, checkpoint every %d" % (n, n, steps, every),
+            "dt_fixed": dt, "J": J.item(), "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3,
+            "ratio": bwd / fwd, "residual_ms": (a1 - a0) * 1e3 / reps, "residual_vjp_ms": (a2 - a1) * 1e3 / reps,
+            "vjp_over_residual": (a2 - a1) / (a1 - a0),
+            "grad_theta": [float(x) for x in theta.grad], "grad_nodes_norm": float(nodes.grad.norm())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +192,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--no-extras", action="store_true", help="skip the batching and adjoint measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (torch copy kernel) to scale HBM byte counters")
     args = ap.parse_args()
@@ -174,7 +261,7 @@ def main():
     finite = bool(torch.isfinite(Q).all().item())
 
     out = {
-        "metric": "FP64 cell-updates/s per RK stage",
+        "metric": "FP64 cell-updates/s per RK stage + % HBM roofline; adjoint/forward time ratio",
         "value": value,
         "unit": "cell-updates/s per RK stage",
         "n_gpus": 1,
@@ -198,6 +285,14 @@ def main():
         "state_finite": finite,
         "kernel_source_sha": sha,
     }
+    if not args.no_extras:
+        s.close()
+        del s, Q
+        torch.cuda.empty_cache()
+        print("[bench] batching: 64-block patchwork, per-block vs batched+graph", file=sys.stderr, flush=True)
+        out["batching"] = bench_batching()
+        print("[bench] adjoint: 512^2 ramp, 50 unrolled steps", file=sys.stderr, flush=True)
+        out["adjoint"] = bench_adjoint()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
