@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-extras", action="store_true", help="skip the batching and adjoint measurements")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="run only the adjoint measurement and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 1 GiB (torch copy kernel) to scale HBM byte counters")
     args = ap.parse_args()
@@ -214,6 +216,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
+    if args.only_adjoint:
+        print(json.dumps(bench_adjoint()))
         return
     case = make_case(args.workload, args.n)
     print("[bench] workload %s, %d cells, building" % (case.name, case.ncells), file=sys.stderr, flush=True)

@@ -398,6 +398,10 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     const long long pk = dim == 3 ? h.nk + 4 : 1;
     const long long padded = (long long)B.pi * B.pj * pk;
     B.vstride = align_ll(padded, 16);
+    // kernels address one array of a block with 32-bit byte offsets
+    if (B.vstride * 8 >= (1LL << 32))
+      return fail(c, CFD_ERR_UNSUPPORTED, "block %d: a padded array exceeds 4 GiB (%lld cells); split the block", b,
+                  padded);
     const long long K = ((dim == 3 ? 2LL * B.pj : 0LL) + 2) * B.pi + 2;  // origin - array base
     // array base at cursor + 14 puts the origin (K = 2 mod 16) on a 16-double boundary
     B.origin = cursor + 14 + K;

@@ -16,10 +16,13 @@
 //      Q^(k) = Q^(0) - alpha dt R(Q^(k-1)) (Sec. 2, M-stage Runge-Kutta) and
 //      stores the new primitive state; the last stage of a step also reduces
 //      Omega / lambda for the next CFL time step.
-// Steps 2 and 3 run the i- and j-items of a plane as one flattened list with a
-// single code path (per-lane addressing), so a wavefront never diverges
-// between directions.  The k direction keeps (q_k, q_k+1, q_k+2, slopes,
-// F_k-1/2) in registers so every k-face flux is computed once.
+// Every thread computes the slopes of its own cell and the fluxes through its
+// own cell's low faces; the halo cells' slopes and the faces on the tile's
+// high edges are a short extra round.  The k direction keeps q_k, q_k+1, the
+// slope of k and F_k-1/2 in registers so every k-face flux is computed once.
+// Global latency is hidden by prefetching: the next plane's halo item and
+// q_k+3 are loaded while the current plane computes, and the own cell's
+// metrics and stage-start state are loaded before the plane's first barrier.
 #pragma once
 
 #include "cfd_internal.h"
@@ -65,6 +68,16 @@ __device__ __forceinline__ bool is_wall(const StageArgs& a, int b, int face, int
   return false;
 }
 
+// Load through a uniform array base and a per-lane 32-bit byte offset (the
+// host guarantees one padded array of a block stays below 4 GiB), so lanes
+// keep one 32-bit offset instead of a 64-bit address per array.
+__device__ __forceinline__ double ld_at(const double* base, unsigned boff) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + boff);
+}
+__device__ __forceinline__ void st_at(double* base, unsigned boff, double x) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + boff) = x;
+}
+
 template <int DIM>
 __device__ __forceinline__ void wall_flux(double pw, const double* S, double* F) {
   F[0] = 0.0;
@@ -73,20 +86,49 @@ __device__ __forceinline__ void wall_flux(double pw, const double* S, double* F)
   F[DIM + 1] = 0.0;
 }
 
+// LDS bytes of one stage-kernel workgroup (must match the arrays below)
+template <int DIM, int LIM, int TX, int TY>
+constexpr int stage_lds_bytes() {
+  constexpr int NV = DIM + 2, NS = LIM == LIM_NONE ? 2 : 1;
+  return 8 * (NV * (TX + 4) * (TY + 4) + NS * NV * (TX + 2) * TY + NS * NV * TX * (TY + 2) + NV * (TX + 1) * TY +
+              NV * TX * (TY + 1) + (DIM == 3 ? NV * TX * TY : 1) + TX * TY / 64);
+}
+// waves per SIMD that the LDS footprint allows (160 KiB per CU, 4 SIMDs); the
+// register allocation is asked to fit the same number
+template <int DIM, int LIM, int TX, int TY>
+constexpr int stage_waves() {
+  constexpr int wg = (160 * 1024) / stage_lds_bytes<DIM, LIM, TX, TY>();
+  constexpr int w = wg * (TX * TY / 64) / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <int DIM, int LIM, int TX, int TY, int KC>
-__global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
+__global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, LIM, TX, TY>())))
+stage_kernel(StageArgs a) {
   constexpr int NV = DIM + 2;
   constexpr int NT = TX * TY;
   constexpr int LX = TX + 4, LY = TY + 4, LP = LX * LY;
   // two slopes per cell only when Psi = 1 (the kappa-form is not symmetric there)
   constexpr int NS = LIM == LIM_NONE ? 2 : 1;
-  constexpr int NSX = (TX + 2) * TY, NSY = TX * (TY + 2), NSL = NSX + NSY;  // slope items
-  constexpr int NFX = (TX + 1) * TY, NFY = TX * (TY + 1), NFL = NFX + NFY;  // face items
+  constexpr int SXW = TX + 2;         // i-slope rows: cells i0-1 .. i0+TX
+  constexpr int NSX = SXW * TY;
+  constexpr int NSY = TX * (TY + 2);  // j-slope rows j0-1 .. j0+TY
+  constexpr int FXW = TX + 1;         // i-face rows: faces i0 .. i0+TX
+  constexpr int NFX = FXW * TY;
+  constexpr int NFY = TX * (TY + 1);  // j-face rows j0 .. j0+TY
+  constexpr int NHALO = 4 * TX + 4 * TY;
+  constexpr int NXS = 2 * TY + 2 * TX;  // slopes of the halo cells
+  constexpr int NXF = TY + TX;          // faces on the tile's high edges
   using ML = MetricLayout<DIM>;
+  constexpr int NH = (NHALO + NT - 1) / NT;  // halo items per thread
+  static_assert(NXS <= NT && NXF <= NT, "tile too flat for one halo slope per thread");
 
   __shared__ double sq[NV][LP];        // plane primitives with halo, [ly][lx]
-  __shared__ double sl[NS][NV][NSL];   // slopes: i-items [r][c] (c: cells i0-1..i0+TX), then j-items
-  __shared__ double fl[NV][NFL];       // fluxes: i-faces [r][f] (f: faces i0..i0+TX), then j-faces [f][c]
+  __shared__ double slx[NS][NV][NSX];  // i-slopes (+, -)
+  __shared__ double sly[NS][NV][NSY];  // j-slopes (+, -)
+  __shared__ double flx[NV][NFX];      // i-face fluxes
+  __shared__ double fly[NV][NFY];      // j-face fluxes
+  __shared__ double fzs[DIM == 3 ? NV : 1][DIM == 3 ? NT : 1];  // lower k-face flux of the own cell
   __shared__ double sred[NT / 64];
 
   const int tid = threadIdx.x;
@@ -99,7 +141,9 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
   const double dt = (a.mode == MODE_STAGE) ? *a.dt : 0.0;
   const double adt = a.alpha * dt;
   const bool q0_is_qin = a.q0 == a.qin;
+  const bool update = a.mode == MODE_STAGE;
   double my_min = 1.0e300;
+  const int own_lp = (ty + 2) * LX + tx + 2;
 
   for (int t = a.tile_begin + blockIdx.x; t < a.tile_end; t += gridDim.x) {
     const TileDev tile = a.tiles[t];
@@ -107,54 +151,96 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
     const int i0 = tile.i0, j0 = tile.j0;
     const int i = i0 + tx, j = j0 + ty;
     const bool own = (i < B.ni) && (j < B.nj);
+    const bool own_in_pad = (i <= B.ni + 1) && (j <= B.nj + 1);
+    // the low faces of the own cell exist up to the block's high faces
+    const bool fx_ok = (i <= B.ni) && (j < B.nj);
+    const bool fy_ok = (i < B.ni) && (j <= B.nj);
     const long long vs = B.vstride;
-    const double* qin = a.qin + B.origin;
-    const double* met = a.metric + B.morigin;
+    const long long plane = (long long)B.pi * B.pj;
+    // array bases (lowest ghost cell of array 0) and byte offsets from them
+    const long long K = (DIM == 3 ? 2LL * B.pj + 2 : 2LL) * B.pi + 2;
+    const double* qin = a.qin + (B.origin - K);
+    const double* met = a.metric + (B.morigin - K);
+    const unsigned p8 = (unsigned)plane * 8u;
     const int kbeg = DIM == 3 ? tile.k0 : 0;
     const int kend = DIM == 3 ? min(tile.k0 + KC, B.nk) : 1;
+    const long long oc = pidx(B, i, j, 0) + K;  // own column, plane 0
+    auto zoff = [&](int k) { return (unsigned)((oc + (long long)k * plane) * 8); };
 
-    // ---- k-direction register queue (3D): cells k (qc), k+1 (qn), k+2 (qnn),
-    // slopes of k (scp/scm) and k+1 (snp/snm), pressure of k-1 (pprev).
-    // The same three steps serve the two-step prologue and the march, so
-    // every k-face flux is formed by identical code wherever it is computed.
-    double qc[NV], qn[NV], qnn[NV], scp[NV], scm[NS == 2 ? NV : 1], snp[NV], snm[NS == 2 ? NV : 1];
-    double fzlo[NV], fzhi[NV];
-    double pprev = 0.0;
-    auto zload_slope = [&](int k) {  // q(k+2) and the slopes of cell k+1
+    // this thread's halo-ring items (the same for every plane of the tile)
+    int hpos[NH];
+    unsigned hoff[NH];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) qnn[v] = qin[v * vs + pidx(B, i, j, k + 2)];
+    for (int h = 0; h < NH; ++h) {
+      const int e0 = tid + h * NT;
+      hpos[h] = -1;
+      hoff[h] = 0;
+      if (e0 < NHALO) {
+        int lx, ly;
+        if (e0 < 4 * TX) {
+          const int r = e0 / TX;
+          lx = 2 + e0 % TX;
+          ly = r < 2 ? r : TY + r;  // rows 0,1 and TY+2, TY+3
+        } else {
+          const int e = e0 - 4 * TX;
+          const int c = e & 3;
+          ly = 2 + (e >> 2);
+          lx = c < 2 ? c : TX + c;  // columns 0,1 and TX+2, TX+3
+        }
+        const int ii = i0 - 2 + lx, jj = j0 - 2 + ly;
+        if (ii <= B.ni + 1 && jj <= B.nj + 1) {
+          hpos[h] = ly * LX + lx;
+          hoff[h] = (unsigned)((pidx(B, ii, jj, 0) + K) * 8);
+        }
+      }
+    }
+    double pre_h[NH][NV];  // prefetched halo values of the next plane
+    auto fetch_halo = [&](int k) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        if (hpos[h] >= 0) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) pre_h[h][v] = ld_at(qin + v * vs, hoff[h] + k * p8);
+        }
+      }
+    };
+
+    // ---- k-direction register queue (3D): cells k (qc), k+1 (qn), slopes of
+    // k (scp/scm) and the prefetched q(k+2) (qnx); the lower k-face flux of
+    // the own cell waits in LDS (only its own thread touches that slot).
+    // Inside a plane q(k) is read back from LDS, so qc is dead there.
+    double qc[NV], qn[NV], qnx[NV], scp[NV], scm[NS == 2 ? NV : 1], fzd[NV];
+    double pprev = 0.0;
+    // slopes of cell k+1 from q(k), q(k+1), q(k+2); flux of face k+1; shift the queue
+    auto zstep = [&](int k, const double* qcur, const double* qnn, const double* Sz, double* F) {
+      double snp[NV], snm[NS == 2 ? NV : 1];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double sp, sm;
-        cell_slopes<LIM>(qn[v] - qc[v], qnn[v] - qn[v], e2[v], kap, sp, sm);
+        cell_slopes<LIM>(qn[v] - qcur[v], qnn[v] - qn[v], e2[v], kap, sp, sm);
         snp[v] = sp;
         if constexpr (NS == 2) snm[v] = sm;
       }
-    };
-    auto zflux = [&](int k, double* F) {  // flux through the k-face k+1 (between cells k and k+1)
-      const int kf = k + 1;
-      double S[3];
+      if (F) {
+        const int kf = k + 1;
+        if (kf == 0 && (B.wall_mask & (1 << 4)) && is_wall(a, tile.block, 4, i, j)) {
+          wall_flux<3>(wall_pressure(qn[NV - 1], qnn[NV - 1]), Sz, F);
+        } else if (kf == B.nk && (B.wall_mask & (1 << 5)) && is_wall(a, tile.block, 5, i, j)) {
+          wall_flux<3>(wall_pressure(qcur[NV - 1], pprev), Sz, F);
+        } else {
+          double L[NV], R[NV];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) S[c] = met[ML::S(2, c) * vs + pidx(B, i, j, kf)];
-      if (kf == 0 && (B.wall_mask & (1 << 4)) && is_wall(a, tile.block, 4, i, j)) {
-        wall_flux<3>(wall_pressure(qn[NV - 1], qnn[NV - 1]), S, F);
-      } else if (kf == B.nk && (B.wall_mask & (1 << 5)) && is_wall(a, tile.block, 5, i, j)) {
-        wall_flux<3>(wall_pressure(qc[NV - 1], pprev), S, F);
-      } else {
-        double L[NV], R[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          L[v] = qc[v] + he * scp[v];
-          if constexpr (NS == 2)
-            R[v] = qn[v] - he * snm[v];
-          else
-            R[v] = qn[v] - he * snp[v];
+          for (int v = 0; v < NV; ++v) {
+            L[v] = qcur[v] + he * scp[v];
+            if constexpr (NS == 2)
+              R[v] = qn[v] - he * snm[v];
+            else
+              R[v] = qn[v] - he * snp[v];
+          }
+          roe_flux<3>(L, R, Sz, a.gas, a.efix, a.half_inv_efix, F);
         }
-        roe_flux<3>(L, R, S, a.gas, a.efix, a.half_inv_efix, F);
       }
-    };
-    auto zrotate = [&]() {
-      pprev = qc[NV - 1];
+      pprev = qcur[NV - 1];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         qc[v] = qn[v];
@@ -165,179 +251,274 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
     };
     if constexpr (DIM == 3) {
       if (own) {
+        double q2[NV], Sz[3];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          qc[v] = qin[v * vs + pidx(B, i, j, kbeg - 2)];
-          qn[v] = qin[v * vs + pidx(B, i, j, kbeg - 1)];
+          qc[v] = ld_at(qin + v * vs, zoff(kbeg - 2));
+          qn[v] = ld_at(qin + v * vs, zoff(kbeg - 1));
         }
-        zload_slope(kbeg - 2);
-        zrotate();
-        zload_slope(kbeg - 1);
-        zflux(kbeg - 1, fzlo);
-        zrotate();
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q2[v] = ld_at(qin + v * vs, zoff(kbeg));
+        zstep(kbeg - 2, qc, q2, nullptr, nullptr);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q2[v] = ld_at(qin + v * vs, zoff(kbeg + 1));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Sz[c] = ld_at(met + ML::S(2, c) * vs, zoff(kbeg));
+        zstep(kbeg - 1, qc, q2, Sz, fzd);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fzs[v][tid] = fzd[v];
+        // queue now: qc = q(kbeg), qn = q(kbeg+1), scp = slope(kbeg)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qnx[v] = ld_at(qin + v * vs, zoff(kbeg + 2));
       }
     }
+    fetch_halo(kbeg);
 
     for (int k = kbeg; k < kend; ++k) {
-      if constexpr (DIM == 3) {
-        if (own) zload_slope(k);
+      const unsigned ok = zoff(k);  // own cell in plane k (byte offset)
+      // own-cell metrics and stage-start state of this plane, consumed after
+      // the slope phase
+      double Sx[DIM], Sy[DIM], Sz[DIM];
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        if (fx_ok) Sx[c] = ld_at(met + ML::S(0, c) * vs, ok);
+        if (fy_ok) Sy[c] = ld_at(met + ML::S(1, c) * vs, ok);
+        if (DIM == 3 && own) Sz[c] = ld_at(met + ML::S(2, c) * vs, ok + p8);
       }
 
       // ---- 1. stage the plane with its halo in LDS ----------------------
       if (DIM == 3 && own) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sq[v][(ty + 2) * LX + tx + 2] = qc[v];
-      } else if (i <= B.ni + 1 && j <= B.nj + 1) {
+        for (int v = 0; v < NV; ++v) sq[v][own_lp] = qc[v];
+      } else if (own_in_pad) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sq[v][(ty + 2) * LX + tx + 2] = qin[v * vs + pidx(B, i, j, k)];
+        for (int v = 0; v < NV; ++v) sq[v][own_lp] = ld_at(qin + v * vs, ok);
       }
-      // halo ring without corners: 2 rows above/below (TX wide), 2 columns left/right (TY tall)
-      for (int e = tid; e < 4 * TX + 4 * TY; e += NT) {
-        int lx, ly;
-        if (e < 4 * TX) {
-          const int r = e / TX;
-          lx = 2 + e % TX;
-          ly = r < 2 ? r : TY + r;  // rows 0,1 and TY+2, TY+3
-        } else {
-          const int e2i = e - 4 * TX;
-          const int c = e2i & 3;
-          ly = 2 + (e2i >> 2);
-          lx = c < 2 ? c : TX + c;  // columns 0,1 and TX+2, TX+3
-        }
-        const int ii = i0 - 2 + lx, jj = j0 - 2 + ly;
-        if (ii <= B.ni + 1 && jj <= B.nj + 1) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) sq[v][ly * LX + lx] = qin[v * vs + pidx(B, ii, jj, k)];
+      for (int h = 0; h < NH; ++h) {
+        if (hpos[h] >= 0) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sq[v][hpos[h]] = pre_h[h][v];
         }
       }
       __syncthreads();
+      // prefetch the next plane's halo while this plane computes
+      if (DIM == 3 && k + 1 < kend) fetch_halo(k + 1);
 
-      // ---- 2. slopes: i-items then j-items, one code path -----------------
-      for (int e = tid; e < NSL; e += NT) {
-        int p, st;
-        if (e < NSX) {
-          const int c = e % (TX + 2), r = e / (TX + 2);
+      // ---- 2. slopes: own cell (i and j), then the halo cells ------------
+      {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double sp, sm;
+          cell_slopes<LIM>(sq[v][own_lp] - sq[v][own_lp - 1], sq[v][own_lp + 1] - sq[v][own_lp], e2[v], kap, sp,
+                           sm);
+          slx[0][v][ty * SXW + tx + 1] = sp;
+          if constexpr (NS == 2) slx[NS - 1][v][ty * SXW + tx + 1] = sm;
+          cell_slopes<LIM>(sq[v][own_lp] - sq[v][own_lp - LX], sq[v][own_lp + LX] - sq[v][own_lp], e2[v], kap, sp,
+                           sm);
+          sly[0][v][(ty + 1) * TX + tx] = sp;
+          if constexpr (NS == 2) sly[NS - 1][v][(ty + 1) * TX + tx] = sm;
+        }
+      }
+      if (tid < NXS) {
+        int p, st, dst;
+        bool isx;
+        if (tid < 2 * TY) {  // i-slopes of cells i0-1 and i0+TX
+          const int r = tid >> 1, side = tid & 1;
+          const int c = side ? TX + 1 : 0;
           p = (r + 2) * LX + c + 1;
           st = 1;
-        } else {
-          const int e2i = e - NSX;
-          const int c = e2i % TX, r = e2i / TX;
+          dst = r * SXW + c;
+          isx = true;
+        } else {  // j-slopes of rows j0-1 and j0+TY
+          const int e = tid - 2 * TY;
+          const int c = e % TX, side = e / TX;
+          const int r = side ? TY + 1 : 0;
           p = (r + 1) * LX + c + 2;
           st = LX;
+          dst = r * TX + c;
+          isx = false;
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double sp, sm;
           cell_slopes<LIM>(sq[v][p] - sq[v][p - st], sq[v][p + st] - sq[v][p], e2[v], kap, sp, sm);
-          sl[0][v][e] = sp;
-          if constexpr (NS == 2) sl[NS - 1][v][e] = sm;
+          if (isx) {
+            slx[0][v][dst] = sp;
+            if constexpr (NS == 2) slx[NS - 1][v][dst] = sm;
+          } else {
+            sly[0][v][dst] = sp;
+            if constexpr (NS == 2) sly[NS - 1][v][dst] = sm;
+          }
         }
       }
       __syncthreads();
 
-      // ---- 3. face fluxes: i-faces then j-faces, one code path ------------
-      for (int e = tid; e < NFL; e += NT) {
-        int pL, st, sL, sR, fi, fj, d, face, t1;
-        bool valid;
-        if (e < NFX) {
-          const int f = e % (TX + 1), r = e / (TX + 1);
-          pL = (r + 2) * LX + f + 1;
+      // ---- 3. face fluxes ---------------------------------------------------
+      // low i-face and low j-face of the own cell (in a ragged tile also the
+      // block's high faces, which are the low faces of its first ghost cells)
+      double F[NV];
+      if (fx_ok) {
+        const int face = i == 0 ? 0 : (i == B.ni ? 1 : -1);
+        if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, j, k)) {
+          const double pw = face == 0 ? wall_pressure(sq[NV - 1][own_lp], sq[NV - 1][own_lp + 1])
+                                      : wall_pressure(sq[NV - 1][own_lp - 1], sq[NV - 1][own_lp - 2]);
+          wall_flux<DIM>(pw, Sx, F);
+        } else {
+          double L[NV], R[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            L[v] = sq[v][own_lp - 1] + he * slx[0][v][ty * SXW + tx];
+            R[v] = sq[v][own_lp] - he * slx[NS - 1][v][ty * SXW + tx + 1];
+          }
+          roe_flux<DIM>(L, R, Sx, a.gas, a.efix, a.half_inv_efix, F);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) flx[v][ty * FXW + tx] = F[v];
+      }
+      if (fy_ok) {
+        const int face = j == 0 ? 2 : (j == B.nj ? 3 : -1);
+        if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, i, k)) {
+          const double pw = face == 2 ? wall_pressure(sq[NV - 1][own_lp], sq[NV - 1][own_lp + LX])
+                                      : wall_pressure(sq[NV - 1][own_lp - LX], sq[NV - 1][own_lp - 2 * LX]);
+          wall_flux<DIM>(pw, Sy, F);
+        } else {
+          double L[NV], R[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            L[v] = sq[v][own_lp - LX] + he * sly[0][v][ty * TX + tx];
+            R[v] = sq[v][own_lp] - he * sly[NS - 1][v][(ty + 1) * TX + tx];
+          }
+          roe_flux<DIM>(L, R, Sy, a.gas, a.efix, a.half_inv_efix, F);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fly[v][ty * TX + tx] = F[v];
+      }
+      // faces on the tile's high edges: i-face i0+TX of each row, j-face j0+TY of each column
+      if (tid < NXF) {
+        int pL, st, sL, sR, fi, fj, d, dst;
+        bool isx;
+        if (tid < TY) {
+          const int r = tid;
+          pL = (r + 2) * LX + TX + 1;
           st = 1;
-          sL = r * (TX + 2) + f;
+          sL = r * SXW + TX;
           sR = sL + 1;
-          fi = i0 + f;
+          fi = i0 + TX;
           fj = j0 + r;
           d = 0;
-          face = fi == 0 ? 0 : (fi == B.ni ? 1 : -1);
-          t1 = fj;
-          valid = fi <= B.ni && fj < B.nj;
+          dst = r * FXW + TX;
+          isx = true;
         } else {
-          const int e2i = e - NFX;
-          const int c = e2i % TX, f = e2i / TX;
-          pL = (f + 1) * LX + c + 2;
+          const int c = tid - TY;
+          pL = (TY + 1) * LX + c + 2;
           st = LX;
-          sL = NSX + f * TX + c;
+          sL = TY * TX + c;
           sR = sL + TX;
           fi = i0 + c;
-          fj = j0 + f;
+          fj = j0 + TY;
           d = 1;
-          face = fj == 0 ? 2 : (fj == B.nj ? 3 : -1);
-          t1 = fi;
-          valid = fi < B.ni && fj <= B.nj;
+          dst = TY * TX + c;
+          isx = false;
         }
+        const bool valid = isx ? (fi <= B.ni && fj < B.nj) : (fi < B.ni && fj <= B.nj);
         if (valid) {
           double S[DIM], F[NV];
-          const long long fidx = pidx(B, fi, fj, k);
+          const unsigned fidx = (unsigned)((pidx(B, fi, fj, k) + K) * 8);
 #pragma unroll
-          for (int c = 0; c < DIM; ++c) S[c] = met[ML::S(d, c) * vs + fidx];
-          if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, t1, k)) {
-            // p0 = cell next to the wall, p1 = the one after it
-            const int pin = (face & 1) ? pL : pL + st;
-            const int dir = (face & 1) ? -st : st;
-            wall_flux<DIM>(wall_pressure(sq[NV - 1][pin], sq[NV - 1][pin + dir]), S, F);
+          for (int c = 0; c < DIM; ++c) S[c] = ld_at(met + ML::S(d, c) * vs, fidx);
+          const int face = isx ? (fi == B.ni ? 1 : -1) : (fj == B.nj ? 3 : -1);
+          if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, isx ? fj : fi, k)) {
+            wall_flux<DIM>(wall_pressure(sq[NV - 1][pL], sq[NV - 1][pL - st]), S, F);
           } else {
             double L[NV], R[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-              L[v] = sq[v][pL] + he * sl[0][v][sL];
-              R[v] = sq[v][pL + st] - he * sl[NS - 1][v][sR];
+              L[v] = sq[v][pL] + he * (isx ? slx[0][v][sL] : sly[0][v][sL]);
+              R[v] = sq[v][pL + st] - he * (isx ? slx[NS - 1][v][sR] : sly[NS - 1][v][sR]);
             }
             roe_flux<DIM>(L, R, S, a.gas, a.efix, a.half_inv_efix, F);
           }
 #pragma unroll
-          for (int v = 0; v < NV; ++v) fl[v][e] = F[v];
+          for (int v = 0; v < NV; ++v) {
+            if (isx)
+              flx[v][dst] = F[v];
+            else
+              fly[v][dst] = F[v];
+          }
         }
       }
+      // inverse volume and stage-start state, consumed after the next barrier
+      double iv = 0.0, w0[NV];
+      if (own) {
+        iv = ld_at(met + ML::INVVOL * vs, ok);
+        if (update && !q0_is_qin) {
+          const double* q0 = a.q0 + (B.origin - K);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) w0[v] = ld_at(q0 + v * vs, ok);
+        }
+      }
+      // k-face k+1 of the own column (queue: q(k) in LDS, q(k+1), q(k+2)), then
+      // the k part of the divergence; prefetch q(k+3) for the next plane
       if constexpr (DIM == 3) {
-        if (own) zflux(k, fzhi);
+        if (own) {
+          double qcur[NV], fz[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) qcur[v] = sq[v][own_lp];
+          zstep(k, qcur, qnx, Sz, fz);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            fzd[v] = fz[v] - fzs[v][tid];
+            fzs[v][tid] = fz[v];
+          }
+          if (k + 1 < kend) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qnx[v] = ld_at(qin + v * vs, ok + 3 * p8);
+          }
+        }
       }
       __syncthreads();
 
       // ---- 4. divergence and update ---------------------------------------
       if (own) {
-        const long long ci = pidx(B, i, j, k);
-        const double iv = met[ML::INVVOL * vs + ci];
-        const int ex = ty * (TX + 1) + tx;  // i-face on this cell's low side
-        const int ey = NFX + ty * TX + tx;  // j-face on this cell's low side
+        const int ex = ty * FXW + tx;
+        const int ey = ty * TX + tx;
         double R[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          double div = (fl[v][ex + 1] - fl[v][ex]) + (fl[v][ey + TX] - fl[v][ey]);
-          if constexpr (DIM == 3) div += fzhi[v] - fzlo[v];
+          double div = (flx[v][ex + 1] - flx[v][ex]) + (fly[v][ey + TX] - fly[v][ey]);
+          if constexpr (DIM == 3) div += fzd[v];
           R[v] = div * iv;
         }
-        if (a.mode == MODE_RESIDUAL) {
+        if (!update) {
           const long long pc = B.packed + ((long long)k * B.nj + j) * B.ni + i;
 #pragma unroll
           for (int v = 0; v < NV; ++v) a.Rout[v * B.ncell_total + pc] = R[v];
         } else {
-          double w[NV], Q[NV], qnew[NV];
+          double Q[NV], qnew[NV];
           if (q0_is_qin) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) w[v] = sq[v][(ty + 2) * LX + tx + 2];
-          } else {
-            const double* q0 = a.q0 + B.origin;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) w[v] = q0[v * vs + ci];
+            for (int v = 0; v < NV; ++v) w0[v] = sq[v][own_lp];
           }
-          prim_to_cons<DIM>(w, a.gas, Q);
+          prim_to_cons<DIM>(w0, a.gas, Q);
 #pragma unroll
           for (int v = 0; v < NV; ++v) Q[v] -= adt * R[v];
           cons_to_prim<DIM>(Q, a.gas, qnew);
-          double* qo = a.qout + B.origin;
+          double* qo = a.qout + (B.origin - K);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) qo[v * vs + ci] = qnew[v];
+          for (int v = 0; v < NV; ++v) st_at(qo + v * vs, ok, qnew[v]);
           if (a.dtmin) {
             // Omega / lambda with lambda = sum_d |u . Sbar_d| + c |Sbar_d|
             const double c = sqrt(a.gas.gamma * qnew[NV - 1] / qnew[0]);
             double lam = 0.0;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-              const long long step = d == 0 ? 1 : (d == 1 ? (long long)B.pi : (long long)B.pi * B.pj);
+              const unsigned step = d == 0 ? 8u : (d == 1 ? 8u * B.pi : p8);
               double un = 0.0, s2 = 0.0;
 #pragma unroll
               for (int cc = 0; cc < DIM; ++cc) {
-                const double sb = 0.5 * (met[ML::S(d, cc) * vs + ci] + met[ML::S(d, cc) * vs + ci + step]);
+                const double* md = met + ML::S(d, cc) * vs;
+                const double sb = 0.5 * (ld_at(md, ok) + ld_at(md, ok + step));
                 un += qnew[1 + cc] * sb;
                 s2 += sb * sb;
               }
@@ -345,14 +526,6 @@ __global__ void __launch_bounds__(TX* TY) stage_kernel(StageArgs a) {
             }
             my_min = fmin(my_min, 1.0 / (lam * iv));
           }
-        }
-      }
-
-      if constexpr (DIM == 3) {
-        if (own) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) fzlo[v] = fzhi[v];
-          zrotate();
         }
       }
       __syncthreads();
