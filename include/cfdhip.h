@@ -211,6 +211,16 @@ cfd_status cfd_adjoint_reset(cfd_ctx* ctx);
  * dev_Qbar holds dJ/dQ^{n+1}, on return dJ/dQ^n; the metric and inflow
  * cotangents of the step accumulate.  Needs CFD_DT_FIXED and at most 4 stages. */
 cfd_status cfd_rk_step_vjp(cfd_ctx* ctx, double* dev_Qbar);
+/* One Runge-Kutta step like cfd_rk_step(ctx, 1, NULL) that also leaves the
+ * ghost-filled inputs Q^(0..M-1) of its M stages in dev_stages: M consecutive
+ * slots of cfd_state_size bytes each (device memory owned by the caller, same
+ * internal layout as cfd_save_state).  Stages 1..M-1 write straight into the
+ * slots; slot 0 is one copy of the step-start state. */
+cfd_status cfd_rk_step_record(cfd_ctx* ctx, void* dev_stages);
+/* cfd_rk_step_vjp for a step recorded by cfd_rk_step_record: the stage states
+ * come from dev_stages instead of being recomputed, and the current state is
+ * neither read nor changed.  Same cotangent conventions and requirements. */
+cfd_status cfd_rk_step_vjp_recorded(cfd_ctx* ctx, const void* dev_stages, double* dev_Qbar);
 /* J = sum over slip-wall faces of p_w |S| (integrated wall pressure) into
  * dev_J[0]; dev_Qbar (nullable) = dJ/dQ; dJ/dS accumulates. */
 cfd_status cfd_objective_wall_pressure(cfd_ctx* ctx, double* dev_J, double* dev_Qbar);

@@ -6,10 +6,10 @@ UnrolledWallPressure J(theta, X) = integrated wall pressure after n Runge-Kutta
                     steps from the uniform state theta (inflow state, also the
                     inflow boundary value) on nodes X.  Forward keeps a
                     checkpoint (bit-exact copy of the solution) every `every`
-                    steps; backward replays each segment from its checkpoint,
-                    keeps the step-start states of that segment, and reverses
-                    the steps with cfd_rk_step_vjp (which recomputes the stage
-                    states of one step and sweeps its stages backwards).
+                    steps; backward replays each segment once from its
+                    checkpoint with cfd_rk_step_record, which keeps the
+                    ghost-filled stage states of every step of the segment,
+                    and reverses the steps with cfd_rk_step_vjp_recorded.
 
 All arithmetic runs in the library's kernels; this module only sequences the
 calls and marshals tensors.
@@ -72,16 +72,14 @@ class UnrolledWallPressure(torch.autograd.Function):
         s.load_state(ctx.final)
         _, Qbar = s.objective_wall_pressure(with_grad=True)
         Qbar = Qbar.contiguous()
+        slots, per = s.stage_record_buffer(ctx.every)
         for (start, buf) in reversed(ctx.ckpts):
             end = min(start + ctx.every, ctx.nsteps)
             s.load_state(buf)
-            states = [s.save_state()]
-            for _ in range(start, end - 1):
-                s.rk_step(1)
-                states.append(s.save_state())
-            for st in reversed(states):
-                s.load_state(st)
-                s.rk_step_vjp(Qbar)
+            for n in range(end - start):
+                s.rk_step_record(slots[n * per:(n + 1) * per])
+            for n in reversed(range(end - start)):
+                s.rk_step_vjp_recorded(slots[n * per:(n + 1) * per], Qbar)
         Xbar, Tbar = s.adjoint_result(nodes=True, inflow=True)
         theta_bar = s.uniform_state_vjp(ctx.th, Qbar) + Tbar[0]
         jb = Jbar.to(s.device)

@@ -70,6 +70,8 @@ SIGNATURES = {
     "cfd_residual_vjp": ([_P, _P, _P, _P, _P], _I),
     "cfd_adjoint_reset": ([_P], _I),
     "cfd_rk_step_vjp": ([_P, _P], _I),
+    "cfd_rk_step_record": ([_P, _P], _I),
+    "cfd_rk_step_vjp_recorded": ([_P, _P, _P], _I),
     "cfd_objective_wall_pressure": ([_P, _P, _P], _I),
     "cfd_adjoint_result": ([_P, _P, _P], _I),
     "cfd_uniform_state_vjp": ([_P, _DP, _P, _P], _I),

@@ -1197,14 +1197,24 @@ extern "C" cfd_status cfd_residual_vjp(cfd_ctx* c, const double* dev_Rbar, doubl
   return cfd_adjoint_result(c, dev_Xbar, dev_BCbar);
 }
 
-extern "C" cfd_status cfd_rk_step_vjp(cfd_ctx* c, double* dev_Qbar) {
+static cfd_status step_vjp_checks(cfd_ctx* c) {
   cfd_status s = need_adjoint(c);
   if (s != CFD_OK) return s;
-  if (!dev_Qbar) return CFD_ERR_ARG;
   if (c->cfg.dt_mode != CFD_DT_FIXED)
     return fail(c, CFD_ERR_UNSUPPORTED, "the step adjoint needs a fixed time step (CFD_DT_FIXED)");
+  if (c->cfg.rk_stages > 4) return fail(c, CFD_ERR_UNSUPPORTED, "the step adjoint keeps at most 4 stage states");
+  return CFD_OK;
+}
+
+// Reverse sweep of one RK step over ghost-filled stage inputs st[0..M-1]
+// (Sec. 2 M-stage scheme: Q^(k) = Q^(0) - dt R(Q^(k-1)) / (M-k+1)).
+static cfd_status reverse_step(cfd_ctx* c, const double* const* st, double* dev_Qbar);
+
+extern "C" cfd_status cfd_rk_step_vjp(cfd_ctx* c, double* dev_Qbar) {
+  cfd_status s = step_vjp_checks(c);
+  if (s != CFD_OK) return s;
+  if (!dev_Qbar) return CFD_ERR_ARG;
   const int M = c->cfg.rk_stages;
-  if (M > 4) return fail(c, CFD_ERR_UNSUPPORTED, "the step adjoint keeps at most 4 stage states");
   double* st[4] = {c->stA(), c->stB(), c->stC(), c->dptr<double>(c->off_stD)};
   // recompute the stage states Q^(1..M-1) of this step from Q^(0) in A
   for (int k = 1; k < M; ++k) {
@@ -1219,6 +1229,56 @@ extern "C" cfd_status cfd_rk_step_vjp(cfd_ctx* c, double* dev_Qbar) {
     if ((s = launch_stage_all(c, a, c->stream, false)) != CFD_OK) return s;
   }
   if ((s = fill_ghosts(c, st[M - 1], c->stream)) != CFD_OK) return s;
+  const double* cst[4] = {st[0], st[1], st[2], st[3]};
+  return reverse_step(c, cst, dev_Qbar);
+}
+
+extern "C" cfd_status cfd_rk_step_record(cfd_ctx* c, void* dev_stages) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!dev_stages) return CFD_ERR_ARG;
+  if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
+  if ((s = ensure_dt(c)) != CFD_OK) return s;
+  const bool cfl = c->cfg.dt_mode == CFD_DT_CFL;
+  hipStream_t hs = c->stream;
+  if (cfl)
+    HIP_TRY(c, launch_dt_promote(c->dptr<double>(c->off_dt), c->dptr<unsigned long long>(c->off_dtmin), c->cfg.cfl,
+                                 1, nullptr, hs));
+  const int M = c->cfg.rk_stages;
+  double* slot0 = static_cast<double*>(dev_stages);
+  double* A = c->stA();
+  if ((s = fill_ghosts(c, A, hs)) != CFD_OK) return s;
+  HIP_TRY(c, hipMemcpyAsync(slot0, A, (size_t)c->state_doubles * 8, hipMemcpyDeviceToDevice, hs));
+  const double* in = A;
+  for (int k = 1; k <= M; ++k) {
+    double* out = (k == M) ? A : slot0 + (size_t)k * c->state_doubles;
+    if (k > 1 && (s = fill_ghosts(c, const_cast<double*>(in), hs)) != CFD_OK) return s;
+    StageArgs a = stage_args(c);
+    a.qin = in;
+    a.q0 = A;
+    a.qout = out;
+    a.mode = MODE_STAGE;
+    a.alpha = 1.0 / (double)(M - k + 1);
+    a.dtmin = (k == M && cfl) ? c->dptr<unsigned long long>(c->off_dtmin) : nullptr;
+    if ((s = launch_stage_all(c, a, hs, false)) != CFD_OK) return s;
+    in = out;
+  }
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_rk_step_vjp_recorded(cfd_ctx* c, const void* dev_stages, double* dev_Qbar) {
+  cfd_status s = step_vjp_checks(c);
+  if (s != CFD_OK) return s;
+  if (!dev_Qbar || !dev_stages) return CFD_ERR_ARG;
+  const double* slot0 = static_cast<const double*>(dev_stages);
+  const double* st[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int k = 0; k < c->cfg.rk_stages; ++k) st[k] = slot0 + (size_t)k * c->state_doubles;
+  return reverse_step(c, st, dev_Qbar);
+}
+
+static cfd_status reverse_step(cfd_ctx* c, const double* const* st, double* dev_Qbar) {
+  cfd_status s = CFD_OK;
+  const int M = c->cfg.rk_stages;
   // reverse sweep: acc (= dev_Qbar) collects dJ/dQ^(0); G is the cotangent of Q^(k)
   const size_t bytes = (size_t)c->nvar * c->ncells * 8;
   double* G = c->dptr<double>(c->off_G);

@@ -42,6 +42,7 @@ class Solver:
         self.lib = capi.load()
         self.dim = dim
         self.nvar = dim + 2
+        self.stages = scheme.rk_stages
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         self.stream = torch.cuda.current_stream(self.device)
@@ -218,6 +219,24 @@ class Solver:
         """In place: Qbar holds dJ/dQ^{n+1} on entry and dJ/dQ^n on return."""
         assert Qbar.is_contiguous() and Qbar.dtype == F64
         self._check(self.lib.cfd_rk_step_vjp(self.ctx, dptr(Qbar)))
+        return Qbar
+
+    def stage_record_buffer(self, nsteps):
+        """Device buffer for the stage states of `nsteps` recorded steps."""
+        per = self.state_bytes() * self.stages
+        return torch.empty(nsteps * per, dtype=torch.uint8, device=self.device), per
+
+    def rk_step_record(self, slots):
+        """One step that leaves its ghost-filled stage inputs in `slots`
+        (a uint8 device tensor of stages * state_bytes())."""
+        assert slots.numel() >= self.state_bytes() * self.stages
+        self._check(self.lib.cfd_rk_step_record(self.ctx, dptr(slots)))
+
+    def rk_step_vjp_recorded(self, slots, Qbar):
+        """rk_step_vjp over the stage states of a recorded step."""
+        assert Qbar.is_contiguous() and Qbar.dtype == F64
+        assert slots.numel() >= self.state_bytes() * self.stages
+        self._check(self.lib.cfd_rk_step_vjp_recorded(self.ctx, dptr(slots), dptr(Qbar)))
         return Qbar
 
     def objective_wall_pressure(self, with_grad=True):

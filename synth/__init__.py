@@ -419,15 +419,17 @@ def split_block_case(case: Case, splits_i: Sequence[int], splits_j: Sequence[int
 # directions for derivative checks
 
 
-def inflow_directions(count: int, seed: int, nvar: int = 4, scale=(1e-2, 1e-2, 1e-2, 1e-2)):
+def inflow_directions(count: int, seed: int, nvar: int = 4):
+    """Seeded unit-norm directions in the space of inflow primitive states."""
     rng = np.random.default_rng(seed)
     d = rng.standard_normal((count, nvar))
-    return d * np.asarray(scale)[None, :nvar]
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
 
 
-def node_displacement_fields(block: Block, count: int, seed: int, amp=0.01, nmodes=3):
-    """Smooth node displacement fields (2D) of amplitude ``amp`` times the
-    local node spacing, nonzero on the wall and in the interior alike."""
+def node_displacement_fields(block: Block, count: int, seed: int, nmodes=3):
+    """Smooth node displacement fields (2D), proportional to the local node
+    spacing, nonzero on the wall and in the interior alike, scaled so the
+    largest displacement component of each field is 1."""
     rng = np.random.default_rng(seed)
     nodes = block.nodes
     nj1, ni1 = nodes.shape[1], nodes.shape[2]
@@ -444,7 +446,8 @@ def node_displacement_fields(block: Block, count: int, seed: int, amp=0.01, nmod
                 a, b = rng.integers(1, 4, size=2)
                 ph = rng.uniform(0, 2 * np.pi, size=2)
                 f += np.sin(np.pi * a * s + ph[0]) * np.cos(np.pi * b * t + ph[1])
-            out[n, c] = amp * np.abs(hc) * f / nmodes
+            out[n, c] = np.abs(hc) * f
+        out[n] /= np.abs(out[n]).max()
     return out
 
 

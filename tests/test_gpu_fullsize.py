@@ -175,13 +175,9 @@ def test_ramp_512_vjp_matches_oracle():
 
 
 def test_ramp_512_unrolled_gradient_vs_central_differences():
-    """20 seeded directions (10 inflow states, 10 smooth node displacements),
-    central differences h = 1e-7 of the HIP forward J against the adjoint.
-
-    The rounding noise of J (a few ulp of |J|) divided by h is about 1e-8 here,
-    so a directional derivative far below the gradient's size cannot be
-    resolved to 1e-6 of itself: the bound is 1e-6 of the larger of |fd| and a
-    tenth of |grad| |d|."""
+    """20 seeded directions (10 unit inflow-state directions, 10 smooth node
+    displacement fields with largest component 1), central differences with
+    h = 1e-7 of the HIP forward J against the adjoint, 1e-6 relative."""
     from paper_2012_02925_amd.autograd import unrolled_wall_pressure
     _say("case: ramp 512x512, 50 steps, FD vs adjoint")
     n, steps = 512, 50
@@ -203,10 +199,6 @@ def test_ramp_512_unrolled_gradient_vs_central_differences():
             return unrolled_wall_pressure(s, theta0 + dth, nodes0 + dX, steps, every=10).item()
 
     h = 1e-7
-
-    def bound(fd, g, d):
-        return 1e-6 * max(abs(fd), 0.1 * g.norm().item() * d.norm().item())
-
     dirs_t = synth.inflow_directions(10, seed=11)
     dirs_x = synth.node_displacement_fields(case.blocks[0], 10, seed=12)
     worst = 0.0
@@ -217,7 +209,7 @@ def test_ramp_512_unrolled_gradient_vs_central_differences():
         rel = abs(fd - ad) / abs(fd)
         worst = max(worst, rel)
         _say("   inflow dir %d: fd %.12e ad %.12e rel %.2e" % (m, fd, ad, rel))
-        assert abs(fd - ad) <= bound(fd, gT, d)
+        assert rel <= 1e-6
     for m in range(10):
         d = torch.tensor(dirs_x[m]).reshape(2, -1).to("cuda:0")
         fd = (Jf(0.0, h * d) - Jf(0.0, -h * d)) / (2 * h)
@@ -225,5 +217,5 @@ def test_ramp_512_unrolled_gradient_vs_central_differences():
         rel = abs(fd - ad) / abs(fd)
         worst = max(worst, rel)
         _say("   node dir %d: fd %.12e ad %.12e rel %.2e" % (m, fd, ad, rel))
-        assert abs(fd - ad) <= bound(fd, gX, d)
+        assert rel <= 1e-6
     _say("   worst relative disagreement", worst)
