@@ -146,11 +146,13 @@ def bench_adjoint(n=512, steps=50, every=10):
     s = Solver.from_case(case, device="cuda:0", adjoint=True)
     theta = torch.tensor(case.meta["inflow"], requires_grad=True)
     nodes = torch.tensor(case.blocks[0].nodes).reshape(2, -1).to("cuda:0").requires_grad_(True)
-    # warm-up pass (graph capture, allocator)
-    J = unrolled_wall_pressure(s, theta, nodes, 4, every)
-    J.backward()
-    theta.grad = None
-    nodes.grad = None
+    # warm-up passes of the same length (graph capture, allocator, stage-record buffer)
+    for _ in range(2):
+        J = unrolled_wall_pressure(s, theta, nodes, steps, every)
+        J.backward()
+        del J
+        theta.grad = None
+        nodes.grad = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     J = unrolled_wall_pressure(s, theta, nodes, steps, every)

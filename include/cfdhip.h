@@ -201,7 +201,9 @@ cfd_status cfd_kernel_time(cfd_ctx* ctx, double* total_ms, long long* launches);
 cfd_status cfd_enable_adjoint(cfd_ctx* ctx, int enable);
 /* dev_Qbar = (dR/dQ)^T dev_Rbar at the current state; if not NULL,
  * dev_Xbar = (dR/dX)^T dev_Rbar (nodes) and dev_BCbar = (dR/dtheta)^T dev_Rbar
- * (inflow states).  Clears the metric/inflow accumulators first. */
+ * (inflow states).  Clears the metric/inflow accumulators first.  dev_Rbar
+ * and dev_Qbar must not overlap (cells are finalized while neighbouring
+ * tiles still read the residual cotangent). */
 cfd_status cfd_residual_vjp(cfd_ctx* ctx, const double* dev_Rbar, double* dev_Qbar, double* dev_Xbar,
                             double* dev_BCbar);
 /* Zero the accumulated node-metric and inflow cotangents. */

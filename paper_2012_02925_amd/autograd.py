@@ -6,10 +6,12 @@ UnrolledWallPressure J(theta, X) = integrated wall pressure after n Runge-Kutta
                     steps from the uniform state theta (inflow state, also the
                     inflow boundary value) on nodes X.  Forward keeps a
                     checkpoint (bit-exact copy of the solution) every `every`
-                    steps; backward replays each segment once from its
-                    checkpoint with cfd_rk_step_record, which keeps the
-                    ghost-filled stage states of every step of the segment,
-                    and reverses the steps with cfd_rk_step_vjp_recorded.
+                    steps and records the stage states of the last segment as
+                    it computes them; backward reverses that segment at once,
+                    then replays each earlier segment from its checkpoint with
+                    cfd_rk_step_record (ghost-filled stage states of every step
+                    of the segment) and reverses it with
+                    cfd_rk_step_vjp_recorded.
 
 All arithmetic runs in the library's kernels; this module only sequences the
 calls and marshals tensors.
@@ -53,13 +55,22 @@ class UnrolledWallPressure(torch.autograd.Function):
         s.set_bc_params(inflow_patch, th)
         s.set_state_primitive(_uniform_prims(s, theta))
         ckpts = []
+        last = ((nsteps - 1) // every) * every if nsteps > 0 else 0
+        slots, per = s.stage_record_buffer(every)
         for n in range(nsteps):
             if n % every == 0:
                 ckpts.append((n, s.save_state()))
-            s.rk_step(1)
+            if n >= last:
+                s.rk_step_record(slots[(n - last) * per:(n - last + 1) * per])
+            else:
+                s.rk_step(1)
         J, _ = s.objective_wall_pressure(with_grad=False)
+        if not any(ctx.needs_input_grad[:2]):  # no backward will follow
+            s.release_record_buffer(slots)
+            slots = None
         ctx.solver, ctx.nsteps, ctx.every, ctx.th = s, nsteps, every, th
         ctx.ckpts = ckpts
+        ctx.slots, ctx.per, ctx.last = slots, per, last
         ctx.final = s.save_state()
         ctx.theta_device = theta.device
         ctx.nodes_shape = nodes.shape
@@ -72,14 +83,17 @@ class UnrolledWallPressure(torch.autograd.Function):
         s.load_state(ctx.final)
         _, Qbar = s.objective_wall_pressure(with_grad=True)
         Qbar = Qbar.contiguous()
-        slots, per = s.stage_record_buffer(ctx.every)
+        slots, per = ctx.slots, ctx.per
         for (start, buf) in reversed(ctx.ckpts):
             end = min(start + ctx.every, ctx.nsteps)
-            s.load_state(buf)
-            for n in range(end - start):
-                s.rk_step_record(slots[n * per:(n + 1) * per])
+            if start != ctx.last:  # the last segment was recorded by the forward pass
+                s.load_state(buf)
+                for n in range(end - start):
+                    s.rk_step_record(slots[n * per:(n + 1) * per])
             for n in reversed(range(end - start)):
                 s.rk_step_vjp_recorded(slots[n * per:(n + 1) * per], Qbar)
+        s.release_record_buffer(slots)
+        ctx.slots = None
         Xbar, Tbar = s.adjoint_result(nodes=True, inflow=True)
         theta_bar = s.uniform_state_vjp(ctx.th, Qbar) + Tbar[0]
         jb = Jbar.to(s.device)

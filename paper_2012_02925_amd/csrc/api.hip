@@ -68,6 +68,8 @@ struct cfd_ctx {
   std::vector<std::vector<TileDev>> tiles_batched, tiles_block;  // per variant
   std::vector<std::vector<int>> tile_begin;                      // per variant, per block (+1)
   std::vector<long long> export_off;
+  long long max_face_area = 0;
+  bool need_bgather = true;  // some boundary cell is left to the boundary gather pass
   long long ncells = 0, nnodes = 0, max_cells = 0, max_padded = 0, max_pos = 0, padded_total = 0, max_faces = 0,
             max_nodes = 0;
   long long state_doubles = 0, metric_doubles = 0, xbuf_doubles = 0;
@@ -93,10 +95,13 @@ struct cfd_ctx {
   bool adjoint = false;
   long long facebar_doubles = 0;
   size_t off_stD = 0, off_qbar = 0, off_facebar = 0, off_metricbar = 0, off_G = 0, off_T = 0, off_thetabar = 0,
-         off_part = 0, off_partoff = 0, off_vjpchunks = 0, off_objchunks = 0, off_inflowlist = 0, off_walllist = 0,
-         off_sumpart = 0, off_J = 0;
-  std::vector<ChunkDev> vjp_chunks, obj_chunks;      // ghost transposes / objective, grouped by donor face
-  std::vector<int> vjp_begin, obj_begin;             // per face (size 2*dim + 1)
+         off_part = 0, off_partoff = 0, off_objchunks = 0, off_inflowlist = 0, off_walllist = 0,
+         off_sumpart = 0, off_J = 0, off_facemap = 0, off_fmapoff = 0, off_vtiles = 0;
+  std::vector<ChunkDev> obj_chunks;                  // objective, grouped by wall face
+  std::vector<int> obj_begin;                        // per face (size 2*dim + 1)
+  std::vector<int> facemap;                          // per block face position: donor transfer or -(patch+1)
+  std::vector<long long> fmap_off;                   // [block * 6 + face]
+  std::vector<TileDev> vtiles;                       // tiles of the fused 2D adjoint pass
   std::vector<long long> part_off;
   std::vector<int> inflow_list, wall_list;
   long long part_doubles = 0;
@@ -562,25 +567,58 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     c->off_tiles_block[v] = take(c->tiles_block[v].size() * sizeof(TileDev));
   }
   if (c->adjoint) {
-    // ghost transposes grouped by donor face: transfers by their donor face,
-    // patches by their own face; one element per tangential position
+    // per block face and tangential position, the item whose ghost cells
+    // copy that position's cells: a transfer (this block as donor) or a patch
     const int nf = 2 * dim;
-    c->vjp_chunks.clear();
+    c->fmap_off.assign((size_t)nb * 6, 0);
+    c->facemap.clear();
+    auto t1ext = [&](int b, int f) { return (f >> 1) == 0 ? c->blocks[b].nj : c->blocks[b].ni; };
+    auto t2ext = [&](int b, int f) { return dim == 3 ? ((f >> 1) == 2 ? c->blocks[b].nj : c->blocks[b].nk) : 1; };
+    for (int b = 0; b < nb; ++b)
+      for (int f = 0; f < nf; ++f) {
+        c->fmap_off[(size_t)b * 6 + f] = (long long)c->facemap.size();
+        c->max_face_area = std::max(c->max_face_area, (long long)t1ext(b, f) * t2ext(b, f));
+        c->facemap.resize(c->facemap.size() + (size_t)t1ext(b, f) * t2ext(b, f), FMAP_NONE);
+      }
+    for (size_t x = 0; x < c->xfers.size(); ++x) {
+      const TransferDev& X = c->xfers[x];
+      const long long base = c->fmap_off[(size_t)X.dblock * 6 + X.dface];
+      const int T1 = t1ext(X.dblock, X.dface);
+      for (int r2 = 0; r2 < X.len1; ++r2)
+        for (int r1 = 0; r1 < X.len0; ++r1) {
+          int d1, d2;
+          orient_map(X.orient, r1, r2, X.dlen0, X.dlen1, d1, d2);
+          c->facemap[base + (X.dlo0 + d1) + (long long)(X.dlo1 + d2) * T1] = (int)x;
+        }
+    }
+    for (size_t p = 0; p < c->patches.size(); ++p) {
+      const PatchDev& P = c->patches[p];
+      const long long base = c->fmap_off[(size_t)P.block * 6 + P.face];
+      const int T1 = t1ext(P.block, P.face);
+      for (int e1 = 0; e1 < P.len1; ++e1)
+        for (int e0 = 0; e0 < P.len0; ++e0)
+          c->facemap[base + (P.lo0 + e0) + (long long)(P.lo1 + e1) * T1] = -(int)p - 1;
+    }
+    // 2D: the tile pass finalizes cells next to physical patches itself; the
+    // boundary gather is needed for connections and for blocks whose last
+    // two cells along an axis fall into different tiles
+    c->need_bgather = dim == 3 || !c->xfers.empty();
+    if (dim == 2)
+      for (int b = 0; b < nb; ++b)
+        if (c->blocks[b].ni % VJP_TILE == 1 || c->blocks[b].nj % VJP_TILE == 1) c->need_bgather = true;
+    c->vtiles.clear();
+    if (dim == 2)
+      for (int b = 0; b < nb; ++b)
+        for (int j0 = 0; j0 < c->blocks[b].nj; j0 += VJP_TILE)
+          for (int i0 = 0; i0 < c->blocks[b].ni; i0 += VJP_TILE) c->vtiles.push_back(TileDev{b, i0, j0, 0});
     c->obj_chunks.clear();
-    c->vjp_begin.assign(nf + 1, 0);
     c->obj_begin.assign(nf + 1, 0);
     for (int f = 0; f < nf; ++f) {
-      c->vjp_begin[f] = (int)c->vjp_chunks.size();
-      for (size_t x = 0; x < c->xfers.size(); ++x)
-        if (c->xfers[x].dface == f) add_chunks(c->vjp_chunks, 0, (int)x, c->xfers[x].len0 * c->xfers[x].len1);
-      for (size_t p = 0; p < c->patches.size(); ++p)
-        if (c->patches[p].face == f) add_chunks(c->vjp_chunks, 1, (int)p, c->patches[p].len0 * c->patches[p].len1);
       c->obj_begin[f] = (int)c->obj_chunks.size();
       for (size_t p = 0; p < c->patches.size(); ++p)
         if (c->patches[p].face == f && c->patches[p].kind == PK_SLIP_WALL)
           add_chunks(c->obj_chunks, 1, (int)p, c->patches[p].len0 * c->patches[p].len1);
     }
-    c->vjp_begin[nf] = (int)c->vjp_chunks.size();
     c->obj_begin[nf] = (int)c->obj_chunks.size();
     c->part_off.assign(c->patches.size(), 0);
     c->inflow_list.clear();
@@ -602,7 +640,9 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     c->off_thetabar = take((size_t)std::max(c->ninflow, 1) * MAXV * 8);
     c->off_part = take(c->part_doubles * 8);
     c->off_partoff = take(c->part_off.size() * sizeof(long long));
-    c->off_vjpchunks = take(c->vjp_chunks.size() * sizeof(ChunkDev));
+    c->off_facemap = take(c->facemap.size() * sizeof(int));
+    c->off_fmapoff = take(c->fmap_off.size() * sizeof(long long));
+    c->off_vtiles = take(std::max<size_t>(c->vtiles.size(), 1) * sizeof(TileDev));
     c->off_objchunks = take(c->obj_chunks.size() * sizeof(ChunkDev));
     c->off_inflowlist = take(c->inflow_list.size() * sizeof(int));
     c->off_walllist = take(c->wall_list.size() * sizeof(int));
@@ -660,7 +700,9 @@ extern "C" cfd_status cfd_bind_workspace(cfd_ctx* c, void* ptr, size_t bytes) {
   }
   if (c->adjoint) {
     if ((s = upload(c, c->off_partoff, c->part_off)) != CFD_OK) return s;
-    if ((s = upload(c, c->off_vjpchunks, c->vjp_chunks)) != CFD_OK) return s;
+    if ((s = upload(c, c->off_facemap, c->facemap)) != CFD_OK) return s;
+    if ((s = upload(c, c->off_fmapoff, c->fmap_off)) != CFD_OK) return s;
+    if ((s = upload(c, c->off_vtiles, c->vtiles)) != CFD_OK) return s;
     if ((s = upload(c, c->off_objchunks, c->obj_chunks)) != CFD_OK) return s;
     if ((s = upload(c, c->off_inflowlist, c->inflow_list)) != CFD_OK) return s;
     if ((s = upload(c, c->off_walllist, c->wall_list)) != CFD_OK) return s;
@@ -1117,8 +1159,15 @@ static VjpArgs vjp_args(cfd_ctx* c, const double* q, const double* Rb, double sc
   a.thetabar = c->dptr<double>(c->off_thetabar);
   a.inflow_part = c->dptr<double>(c->off_part);
   a.part_offset = c->dptr<long long>(c->off_partoff);
+  a.facemap = c->dptr<int>(c->off_facemap);
+  a.fmap_off = c->dptr<long long>(c->off_fmapoff);
+  a.vtiles = c->dptr<TileDev>(c->off_vtiles);
+  a.inflow_list = c->dptr<int>(c->off_inflowlist);
+  a.ninflow = (int)c->inflow_list.size();
   a.out = out;
   a.acc = acc;
+  a.acc_mode = 1;
+  a.tile_bc = 0;
   a.scale = scale;
   a.gas = make_gas(c->cfg.gamma);
   a.half_eps = 0.5 * c->cfg.muscl_eps;
@@ -1139,22 +1188,32 @@ static cfd_status need_adjoint(cfd_ctx* c) {
 
 // Residual VJP at state buffer q (ghosts filled): out = scale * (dR/dQ)^T Rb,
 // acc += the same; scale * dJ/dS, dJ/dOmega, dJ/dtheta accumulate.
-static cfd_status vjp_core(cfd_ctx* c, const double* q, const double* Rb, double scale, double* out, double* acc) {
+// One residual VJP at state q: out = scale (dR/dQ)^T Rb and acc += the parts
+// selected by acc_mode (bit 0: that product, bit 1: Rb itself).  Rb must not
+// alias out or acc.
+static cfd_status vjp_core(cfd_ctx* c, const double* q, const double* Rb, double scale, double* out, double* acc,
+                           int acc_mode = 1) {
   const int nb = (int)c->blocks.size();
   VjpArgs a = vjp_args(c, q, Rb, scale, out, acc);
+  a.acc_mode = acc_mode;
   hipStream_t s = c->stream;
-  HIP_TRY(c, launch_vjp_face(c->dim, c->cfg.limiter, a, c->max_faces, nb, s));
-  HIP_TRY(c, launch_vjp_cell(c->dim, c->cfg.limiter, a, c->max_padded, nb, s));
-  for (int f = 0; f < 2 * c->dim; ++f)
-    HIP_TRY(c, launch_vjp_ghost(c->dim, a, c->dptr<ChunkDev>(c->off_vjpchunks), c->vjp_begin[f],
-                                c->vjp_begin[f + 1] - c->vjp_begin[f], s));
-  HIP_TRY(c, launch_vjp_finalize(c->dim, a, c->max_cells, nb, s));
-  HIP_TRY(c, launch_vjp_inflow_reduce(c->dim, a, c->dptr<int>(c->off_inflowlist), (int)c->inflow_list.size(), s));
+  if (c->dim == 2) {
+    a.tile_bc = 1;
+    HIP_TRY(c, launch_vjp_tile2d(c->cfg.limiter, a, (int)c->vtiles.size(), s));
+  } else {
+    HIP_TRY(c, launch_vjp_face(c->dim, c->cfg.limiter, a, c->max_faces, nb, s));
+    HIP_TRY(c, launch_vjp_cell(c->dim, c->cfg.limiter, a, c->max_padded, nb, s));
+  }
+  if (c->need_bgather) HIP_TRY(c, launch_vjp_boundary_gather(c->dim, a, c->max_face_area, nb, s));
   return CFD_OK;
 }
 
 static cfd_status copy_thetabar(cfd_ctx* c, double* dev_BCbar) {
   if (!dev_BCbar || c->ninflow == 0) return CFD_OK;
+  // dJ/dtheta = sum of the per-position partials accumulated since the reset
+  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_thetabar, 0, (size_t)std::max(c->ninflow, 1) * MAXV * 8, c->stream));
+  VjpArgs a = vjp_args(c, c->stA(), nullptr, 1.0, nullptr, nullptr);
+  HIP_TRY(c, launch_vjp_inflow_reduce(c->dim, a, c->stream));
   HIP_TRY(c, hipMemcpy2DAsync(dev_BCbar, c->nvar * 8, c->dptr<double>(c->off_thetabar), MAXV * 8, c->nvar * 8,
                               c->ninflow, hipMemcpyDeviceToDevice, c->stream));
   return CFD_OK;
@@ -1173,7 +1232,7 @@ extern "C" cfd_status cfd_adjoint_reset(cfd_ctx* c) {
   if (s != CFD_OK) return s;
   if (!c->adjoint) return fail(c, CFD_ERR_STATE, "adjoint not enabled");
   HIP_TRY(c, hipMemsetAsync(c->ws + c->off_metricbar, 0, c->metric_doubles * 8, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_thetabar, 0, (size_t)std::max(c->ninflow, 1) * MAXV * 8, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_part, 0, c->part_doubles * 8, c->stream));
   return CFD_OK;
 }
 
@@ -1279,15 +1338,21 @@ extern "C" cfd_status cfd_rk_step_vjp_recorded(cfd_ctx* c, const void* dev_stage
 static cfd_status reverse_step(cfd_ctx* c, const double* const* st, double* dev_Qbar) {
   cfd_status s = CFD_OK;
   const int M = c->cfg.rk_stages;
-  // reverse sweep: acc (= dev_Qbar) collects dJ/dQ^(0); G is the cotangent of Q^(k)
-  const size_t bytes = (size_t)c->nvar * c->ncells * 8;
+  // reverse sweep.  With G_k the cotangent of Q^(k) (G_M = dev_Qbar on entry)
+  // and V_k = -dt/(M-k+1) (dR/dQ)^T G_k at Q^(k-1): G_{k-1} = V_k for k > 1, and
+  // dJ/dQ^(0) = G_M + ... + G_1 + V_1, accumulated in dev_Qbar.
   double* G = c->dptr<double>(c->off_G);
   double* T = c->dptr<double>(c->off_T);
-  HIP_TRY(c, hipMemcpyAsync(G, dev_Qbar, bytes, hipMemcpyDeviceToDevice, c->stream));
   const double dt = c->cfg.dt_fixed;
-  for (int k = M; k >= 1; --k) {
+  if (M == 1) {
+    const size_t bytes = (size_t)c->nvar * c->ncells * 8;
+    HIP_TRY(c, hipMemcpyAsync(G, dev_Qbar, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return vjp_core(c, st[0], G, -dt, nullptr, dev_Qbar, 1);
+  }
+  if ((s = vjp_core(c, st[M - 1], dev_Qbar, -dt, G, nullptr, 0)) != CFD_OK) return s;
+  for (int k = M - 1; k >= 1; --k) {
     const double sc = -dt / (double)(M - k + 1);
-    if ((s = vjp_core(c, st[k - 1], G, sc, k > 1 ? T : nullptr, dev_Qbar)) != CFD_OK) return s;
+    if ((s = vjp_core(c, st[k - 1], G, sc, k > 1 ? T : nullptr, dev_Qbar, k > 1 ? 2 : 3)) != CFD_OK) return s;
     std::swap(G, T);
   }
   return CFD_OK;

@@ -52,6 +52,7 @@ class Solver:
                                   ctypes.byref(ctx)))
         self.ctx = ctx
         self.workspace = None
+        self._record_pool = []
         self.block_shapes = []
         self.patch_ids = []
         self.patch_kinds = []
@@ -222,9 +223,19 @@ class Solver:
         return Qbar
 
     def stage_record_buffer(self, nsteps):
-        """Device buffer for the stage states of `nsteps` recorded steps."""
+        """Device buffer for the stage states of `nsteps` recorded steps (taken
+        from this solver's pool of released buffers when one is large enough)."""
         per = self.state_bytes() * self.stages
-        return torch.empty(nsteps * per, dtype=torch.uint8, device=self.device), per
+        need = nsteps * per
+        for n, buf in enumerate(self._record_pool):
+            if buf.numel() >= need:
+                return self._record_pool.pop(n), per
+        return torch.empty(need, dtype=torch.uint8, device=self.device), per
+
+    def release_record_buffer(self, buf):
+        """Return a buffer from stage_record_buffer to the pool."""
+        if buf is not None:
+            self._record_pool.append(buf)
 
     def rk_step_record(self, slots):
         """One step that leaves its ghost-filled stage inputs in `slots`
