@@ -15,6 +15,11 @@ Prints one JSON line:
              per launch (190 B per cell-stage in 3D, 128 B in 2D, see the
              design notes) / mean launch time from HIP events recorded on the
              library's stream around every stage launch of the timed region
+  fp64       the same launches against the FP64 vector peak, with the FP64
+             operations per launch counted by rocprofv3 (FMA = 2) for this
+             kernel source, when such a count is on record
+  copy_gbs   a 1 GiB device-to-device copy on the same GPU (a practical HBM
+             ceiling, for context)
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
 """
 import argparse
@@ -29,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 BYTES_PER_CELL_STAGE = {2: 128.0, 3: 190.0}  # mean over the 4 stages, metrics stored
 
 
@@ -49,6 +55,25 @@ def load_traffic(name, sha):
     if t.get("kernel_source_sha") != sha:
         return None
     return t
+
+
+def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
+    """Read+write bandwidth of a plain device copy (torch's copy kernel)."""
+    import torch
+
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def make_case(workload, n):
@@ -263,9 +288,9 @@ def main():
     sha = kernel_source_sha()
     kname = "stage_kernel_%s" % case.name
     traffic = load_traffic(kname, sha)
-    # conservation check of the run (property at any size): total mass drift
     Q = s.get_state()
     finite = bool(torch.isfinite(Q).all().item())
+    copy_gbs = copy_ceiling_gbs()
 
     out = {
         "metric": "FP64 cell-updates/s per RK stage + % HBM roofline; adjoint/forward time ratio",
@@ -288,10 +313,16 @@ def main():
                      "traffic": None if traffic is None else traffic["bytes_per_launch"],
                      "kernel": "cfd::stage_kernel", "bytes_per_cell_stage": BYTES_PER_CELL_STAGE[dim],
                      "mean_launch_ms": mean_launch_s * 1e3, "launches": launches},
+        "copy_gbs": copy_gbs,
         "graph_ms_per_step": (g1 - g0) * 1e3 / args.steps,
         "state_finite": finite,
         "kernel_source_sha": sha,
     }
+    if traffic is not None and traffic.get("fp64_flops_per_launch"):
+        fl = traffic["fp64_flops_per_launch"] / mean_launch_s / 1e12
+        out["fp64"] = {"achieved": fl, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": fl / FP64_VECTOR_PEAK_TFLOPS,
+                       "flops_per_cell_stage": traffic["fp64_flops_per_launch"] / cells}
     if not args.no_extras:
         s.close()
         del s, Q
