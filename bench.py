@@ -152,6 +152,36 @@ def bench_batching(steps=20, warmup=2):
     return out
 
 
+def bench_flux_variants(workload, n, variant, steps=5, warmup=2):
+    """Same workload and tile variant with each face flux (Roe, van Leer and
+    Steger-Warming flux-vector splitting): mean stage-kernel time from HIP
+    events and the resulting cell-updates/s per stage (the paper compares Roe
+    with van Leer's splitting in Sec. 7.2)."""
+    import torch
+
+    from paper_2012_02925_amd.solver import Solver
+
+    out = {}
+    for flux in ("roe", "vanleer_fvs", "steger_warming"):
+        case = make_case(workload, n)
+        case.scheme.flux = flux
+        s = Solver.from_case(case, device="cuda:0")
+        s.set_variant(variant)
+        s.rk_step(warmup)
+        s.profile(True)
+        torch.cuda.synchronize()
+        s.rk_step(steps)
+        kms, launches = s.kernel_time()
+        s.profile(False)
+        ms = kms / max(launches, 1)
+        out[flux] = {"stage_kernel_ms": ms, "cell_updates_per_s": case.ncells / (ms * 1e-3),
+                     "hbm_frac": BYTES_PER_CELL_STAGE[case.dim] * case.ncells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_adjoint(n=512, steps=50, every=10):
     """2D ramp n x n, van Albada (eps 1e-2), Roe, RK4 with the CFL step of the
     initial state held fixed; objective = integrated wall pressure after
@@ -331,6 +361,8 @@ def main():
         out["batching"] = bench_batching()
         print("[bench] adjoint: 512^2 ramp, 50 unrolled steps", file=sys.stderr, flush=True)
         out["adjoint"] = bench_adjoint()
+        print("[bench] face-flux variants on the same workload", file=sys.stderr, flush=True)
+        out["flux_variants"] = bench_flux_variants(args.workload, args.n, out["config"]["tile_variant"])
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

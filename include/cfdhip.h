@@ -60,6 +60,10 @@ typedef enum {
 } cfd_status;
 
 enum { CFD_LIM_NONE = 0, CFD_LIM_VANLEER = 1, CFD_LIM_VANALBADA = 2 };
+/* Face flux.  ROE: rotated Roe flux with Harten smoothing (efix).  VANLEER_FVS:
+ * F = A (F+(qL) + F-(qR)) with van Leer's Mach-number polynomial split;
+ * STEGER_WARMING: the same with F+- = R diag((l +- |l|)/2) R^-1 Q (closed form). */
+enum { CFD_FLUX_ROE = 0, CFD_FLUX_VANLEER_FVS = 1, CFD_FLUX_STEGER_WARMING = 2 };
 enum { CFD_BC_SLIP_WALL = 1, CFD_BC_SUP_INFLOW = 2, CFD_BC_EXTRAP_OUTFLOW = 3 };
 enum { CFD_DT_CFL = 0, CFD_DT_FIXED = 1 };
 /* execution modes for cfd_set_exec */
@@ -78,6 +82,9 @@ typedef struct {
   int dt_mode;          /* CFD_DT_CFL: global CFL step from Q^n each step; CFD_DT_FIXED */
   double cfl;           /* CFL number for CFD_DT_CFL */
   double dt_fixed;      /* time step for CFD_DT_FIXED */
+  int flux;             /* CFD_FLUX_*: inviscid face flux (Sec. 2 lists Roe's flux-difference
+                           splitting and van Leer's and Steger-Warming's flux-vector
+                           splittings); the residual VJP needs CFD_FLUX_ROE */
 } cfd_config;
 
 /* Version string of the library build. */

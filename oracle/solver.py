@@ -3,8 +3,9 @@
 * Residual: finite-volume form of eq. (1), Sec. 2, inviscid part with no
   source: for every cell, R = (1/Omega) sum over its faces of the outward
   numerical flux times area, so that dQ/dt = -R.  Faces are visited one index
-  direction at a time: MUSCL face states (muscl.face_states) and the Roe flux
-  (roe.roe_flux) on every face of the direction, then the flux difference.
+  direction at a time: MUSCL face states (muscl.face_states) and the scheme's
+  face flux (roe.roe_flux by default, or a flux-vector splitting of fvs) on
+  every face of the direction, then the flux difference.
 * Wall faces: Sec. 7.2 V7 overwrites the Riemann flux on wall faces after the
   boundary enforcement.  Reading: F = (0, p_w S, 0) with the wall pressure
   extrapolated linearly in index space, p_w = 1.5 p_0 - 0.5 p_1 (p_0 the cell
@@ -21,7 +22,7 @@ from __future__ import annotations
 
 import torch
 
-from . import gas, metrics as metrics_mod, muscl, roe
+from . import fvs, gas, metrics as metrics_mod, muscl, roe
 from .ghosts import face_area_slab, fill_ghosts, interior_layer, tangential_axes, tensor_axis
 
 F64 = torch.float64
@@ -49,6 +50,7 @@ class Problem:
         self.eps = sch.muscl_eps
         self.kappa = sch.muscl_kappa
         self.efix = sch.efix
+        self.flux = getattr(sch, "flux", "roe")
         self.stages = sch.rk_stages
         self.cfl = sch.cfl
         self.dt_fixed = sch.dt_fixed
@@ -87,7 +89,7 @@ class Problem:
                     sl[tensor_axis(nd, a)] = slice(2, -2)
             qd = qpad[tuple(sl)]
             qL, qR = muscl.face_states(qd, ax, self.limiter, self.eps, self.kappa, eps2)
-            F = roe.roe_flux(qL, qR, S[d], self.gamma, self.efix)
+            F = self.face_flux(qL, qR, S[d])
             for (face, lo, hi) in walls:
                 if face // 2 != d:
                     continue
@@ -95,6 +97,17 @@ class Problem:
             n = F.shape[ax] - 1
             div = div + (F.narrow(ax, 1, n) - F.narrow(ax, 0, n))
         return div / vol
+
+    def face_flux(self, qL, qR, S):
+        """Inviscid face flux of the scheme: Roe (default), van Leer or
+        Steger-Warming flux-vector splitting."""
+        if self.flux == "roe":
+            return roe.roe_flux(qL, qR, S, self.gamma, self.efix)
+        if self.flux == "vanleer_fvs":
+            return fvs.van_leer_flux(qL, qR, S, self.gamma)
+        if self.flux == "steger_warming":
+            return fvs.steger_warming_flux(qL, qR, S, self.gamma)
+        raise ValueError("unknown flux %s" % self.flux)
 
     def _wall_override(self, F, qpad, Sd, face, lo, hi):
         dim, nd = self.dim, F.ndim

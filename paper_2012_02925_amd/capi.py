@@ -13,6 +13,7 @@ CFD_OK = 0
 STATUS = {0: "CFD_OK", -1: "CFD_ERR_ARG", -2: "CFD_ERR_STATE", -3: "CFD_ERR_TOPOLOGY", -4: "CFD_ERR_GRID",
           -5: "CFD_ERR_HIP", -6: "CFD_ERR_NONFINITE", -7: "CFD_ERR_UNSUPPORTED"}
 LIM = {"none": 0, "vanleer": 1, "vanalbada": 2}
+FLUX = {"roe": 0, "vanleer_fvs": 1, "steger_warming": 2}
 BC = {"slip_wall": 1, "sup_inflow": 2, "extrap_outflow": 3}
 DT_CFL, DT_FIXED = 0, 1
 EXEC_BATCHED, EXEC_PER_BLOCK = 0, 1
@@ -24,7 +25,8 @@ class CfdConfig(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("gamma", ctypes.c_double), ("limiter", ctypes.c_int),
                 ("muscl_eps", ctypes.c_double), ("muscl_kappa", ctypes.c_double),
                 ("lim_eps", ctypes.c_double * 5), ("efix", ctypes.c_double), ("rk_stages", ctypes.c_int),
-                ("dt_mode", ctypes.c_int), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double)]
+                ("dt_mode", ctypes.c_int), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
+                ("flux", ctypes.c_int)]
 
 
 class CfdError(RuntimeError):

@@ -159,6 +159,8 @@ Gas make_gas(double gamma) {
   g.gm1 = gamma - 1.0;
   g.igm1 = 1.0 / (gamma - 1.0);
   g.g_gm1 = gamma / (gamma - 1.0);
+  g.ig = 1.0 / gamma;
+  g.ig2m1 = 1.0 / (gamma * gamma - 1.0);
   return g;
 }
 
@@ -216,6 +218,7 @@ extern "C" cfd_status cfd_create(const cfd_config* cfg, void* stream, cfd_ctx** 
   if (cfg->dim != 2 && cfg->dim != 3) return CFD_ERR_ARG;
   if (!(cfg->gamma > 1.0)) return CFD_ERR_ARG;
   if (cfg->limiter < CFD_LIM_NONE || cfg->limiter > CFD_LIM_VANALBADA) return CFD_ERR_ARG;
+  if (cfg->flux < CFD_FLUX_ROE || cfg->flux > CFD_FLUX_STEGER_WARMING) return CFD_ERR_ARG;
   if (cfg->rk_stages < 1 || cfg->rk_stages > 8) return CFD_ERR_ARG;
   if (cfg->dt_mode == CFD_DT_CFL && !(cfg->cfl > 0.0)) return CFD_ERR_ARG;
   if (cfg->dt_mode == CFD_DT_FIXED && !(cfg->dt_fixed > 0.0)) return CFD_ERR_ARG;
@@ -355,6 +358,8 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   if (!c) return CFD_ERR_ARG;
   if (c->finalized) return fail(c, CFD_ERR_STATE, "already finalized");
   if (c->hblocks.empty()) return fail(c, CFD_ERR_STATE, "no blocks");
+  if (c->adjoint && c->cfg.flux != CFD_FLUX_ROE)
+    return fail(c, CFD_ERR_UNSUPPORTED, "the residual VJP is implemented for the Roe flux");
   const int dim = c->dim, nv = c->nvar;
   const int nb = (int)c->hblocks.size();
 
@@ -844,13 +849,13 @@ static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool 
     for (int b = 0; b < nb; ++b) {
       a.tile_begin = c->tile_begin[v][b];
       a.tile_end = c->tile_begin[v][b + 1];
-      HIP_TRY(c, launch_stage(c->dim, c->cfg.limiter, v, a, a.tile_end - a.tile_begin, s));
+      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->cfg.limiter, v, a, a.tile_end - a.tile_begin, s));
     }
   } else {
     a.tiles = c->dptr<TileDev>(c->off_tiles_batched[v]);
     a.tile_begin = 0;
     a.tile_end = (int)c->tiles_batched[v].size();
-    HIP_TRY(c, launch_stage(c->dim, c->cfg.limiter, v, a, a.tile_end, s));
+    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->cfg.limiter, v, a, a.tile_end, s));
   }
   if (timed) {
     HIP_TRY(c, hipEventRecord(ev->b, s));

@@ -10,6 +10,7 @@ namespace cfd {
 
 struct Gas {
   double gamma, gm1, igm1, g_gm1;  // gamma, gamma-1, 1/(gamma-1), gamma/(gamma-1)
+  double ig, ig2m1;                // 1/gamma, 1/(gamma^2-1)
 };
 
 // Reciprocal and reciprocal square root from the hardware estimates (about
@@ -35,6 +36,15 @@ __device__ __forceinline__ double rcp2(double x) {
 
 __device__ __forceinline__ double rsq(double x) {
   const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-(x * y), y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// Two Newton steps: the flux-vector splittings scale fluxes by |S| and n, so a
+// uniform state's face fluxes sum to zero over a cell only to the accuracy of
+// |S| n = S.
+__device__ __forceinline__ double rsq2(double x) {
+  const double y = rsq(x);
   const double e = fma(-(x * y), y, 1.0);
   return fma(0.5 * y, e, y);
 }
@@ -210,6 +220,114 @@ __device__ __forceinline__ void roe_flux(const double* qL, const double* qR, con
   }
   const double De = (W - w2) * Ht + Wc * Vt + w2 * 0.5 * q2t + ws * (udu - Vt * dV);
   F[NV - 1] = 0.5 * (mL * HL + mR * HR) - hA * De;
+}
+
+// ---------------------------------------------------------------------------
+// Flux-vector splittings (Sec. 2 lists van Leer's and Steger and Warming's;
+// textbook forms).  Face flux A (F+(qL) + F-(qR)) with A = |S|, n = S / A.
+
+enum { FLUX_ROE = 0, FLUX_VANLEER_FVS = 1, FLUX_STEGER_WARMING = 2 };
+
+// Steger-Warming part F+ (sign = 1) or F- (sign = -1) per unit area, added to F:
+// F+- = rho/(2 gamma) [a, a u + c (l3 - l1) n, a |u|^2/2 + c V (l3 - l1) + c^2 (l1 + l3)/(gamma-1)],
+// a = 2 (gamma-1) l2 + l1 + l3, each eigenvalue l1,2,3 = V - c, V, V + c taken as (l +- |l|)/2.
+template <int DIM>
+__device__ __forceinline__ void steger_warming_part(const double* q, const double* n, double sign, const Gas& g,
+                                                    double* F) {
+  constexpr int NV = DIM + 2;
+  const double rho = q[0], p = q[NV - 1];
+  const double c2 = g.gamma * p * rcp(rho);
+  const double c = c2 * rsq(c2);
+  double V = 0.0, q2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    V += q[1 + d] * n[d];
+    q2 += q[1 + d] * q[1 + d];
+  }
+  const double l1 = 0.5 * ((V - c) + sign * fabs(V - c));
+  const double l2 = 0.5 * (V + sign * fabs(V));
+  const double l3 = 0.5 * ((V + c) + sign * fabs(V + c));
+  const double a = 2.0 * g.gm1 * l2 + l1 + l3;
+  const double k = 0.5 * rho * g.ig;
+  const double d31 = c * (l3 - l1);
+  F[0] += k * a;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) F[1 + d] += k * (a * q[1 + d] + d31 * n[d]);
+  F[NV - 1] += k * (a * 0.5 * q2 + d31 * V + c2 * (l1 + l3) * g.igm1);
+}
+
+// van Leer part per unit area, added to F: the full flux beyond Mach 1 on its
+// own side, nothing beyond Mach 1 on the other, else with M = V/c and the mass
+// flux f = +-rho c (M +- 1)^2 / 4:
+// F+- = f [1, u + n (-V +- 2c)/gamma, (|u|^2 - V^2)/2 + ((gamma-1) V +- 2c)^2 / (2 (gamma^2 - 1))].
+template <int DIM>
+__device__ __forceinline__ void van_leer_part(const double* q, const double* n, double sign, const Gas& g,
+                                              double* F) {
+  constexpr int NV = DIM + 2;
+  const double rho = q[0], p = q[NV - 1];
+  const double irho = rcp(rho);
+  const double c2 = g.gamma * p * irho;
+  const double ic = rsq(c2);
+  const double c = c2 * ic;
+  double V = 0.0, q2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    V += q[1 + d] * n[d];
+    q2 += q[1 + d] * q[1 + d];
+  }
+  const double M = V * ic;
+  const double sM = sign * M;
+  if (sM >= 1.0) {  // supersonic towards this side: the whole flux
+    F[0] += rho * V;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) F[1 + d] += rho * q[1 + d] * V + p * n[d];
+    F[NV - 1] += (g.g_gm1 * p + 0.5 * rho * q2) * V;
+  } else if (sM > -1.0) {
+    const double mp = M + sign;
+    const double f = sign * 0.25 * rho * c * mp * mp;
+    const double vn = (-V + sign * 2.0 * c) * g.ig;
+    const double t = g.gm1 * V + sign * 2.0 * c;
+    F[0] += f;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) F[1 + d] += f * (q[1 + d] + vn * n[d]);
+    F[NV - 1] += f * (0.5 * (q2 - V * V) + 0.5 * t * t * g.ig2m1);
+  }
+}
+
+template <int DIM, int FLUX>
+__device__ __forceinline__ void fvs_flux(const double* qL, const double* qR, const double* S, const Gas& g,
+                                         double* F) {
+  constexpr int NV = DIM + 2;
+  double A2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) A2 += S[d] * S[d];
+  const double iA = rsq2(A2);
+  const double A = A2 * iA;
+  double n[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) n[d] = S[d] * iA;
+  double G[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) G[v] = 0.0;
+  if constexpr (FLUX == FLUX_VANLEER_FVS) {
+    van_leer_part<DIM>(qL, n, 1.0, g, G);
+    van_leer_part<DIM>(qR, n, -1.0, g, G);
+  } else {
+    steger_warming_part<DIM>(qL, n, 1.0, g, G);
+    steger_warming_part<DIM>(qR, n, -1.0, g, G);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) F[v] = A * G[v];
+}
+
+// face flux of the configured scheme
+template <int DIM, int FLUX>
+__device__ __forceinline__ void face_flux(const double* qL, const double* qR, const double* S, const Gas& g,
+                                          double efix, double half_inv_efix, double* F) {
+  if constexpr (FLUX == FLUX_ROE)
+    roe_flux<DIM>(qL, qR, S, g, efix, half_inv_efix, F);
+  else
+    fvs_flux<DIM, FLUX>(qL, qR, S, g, F);
 }
 
 }  // namespace cfd

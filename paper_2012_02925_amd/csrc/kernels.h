@@ -46,7 +46,7 @@ struct StageVariant {
 };
 
 const StageVariant* stage_variants(int dim, int* count);
-hipError_t launch_stage(int dim, int lim, int variant, const StageArgs& a, int grid, hipStream_t s);
+hipError_t launch_stage(int dim, int flux, int lim, int variant, const StageArgs& a, int grid, hipStream_t s);
 hipError_t launch_ghost(int dim, const GhostArgs& a, int nchunks, hipStream_t s);
 hipError_t launch_set_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
 hipError_t launch_get_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);

@@ -346,19 +346,28 @@ __global__ void export_padded_kernel(CellArgs a) {
 // ---------------------------------------------------------------------------
 // stage kernel variants
 
-template <int DIM, int LIM, int TX, int TY, int KC>
+template <int DIM, int LIM, int TX, int TY, int KC, int FLUX>
 static hipError_t launch_stage_t(const StageArgs& a, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC>), dim3(grid), dim3(TX * TY), 0, s, a);
+  hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC, FLUX>), dim3(grid), dim3(TX * TY), 0, s, a);
   return hipGetLastError();
 }
 
-template <int DIM, int TX, int TY, int KC>
+template <int DIM, int TX, int TY, int KC, int FLUX>
 static hipError_t launch_stage_lim(int lim, const StageArgs& a, int grid, hipStream_t s) {
   switch (lim) {
-    case LIM_NONE: return launch_stage_t<DIM, LIM_NONE, TX, TY, KC>(a, grid, s);
-    case LIM_VANLEER: return launch_stage_t<DIM, LIM_VANLEER, TX, TY, KC>(a, grid, s);
-    default: return launch_stage_t<DIM, LIM_VANALBADA, TX, TY, KC>(a, grid, s);
+    case LIM_NONE: return launch_stage_t<DIM, LIM_NONE, TX, TY, KC, FLUX>(a, grid, s);
+    case LIM_VANLEER: return launch_stage_t<DIM, LIM_VANLEER, TX, TY, KC, FLUX>(a, grid, s);
+    default: return launch_stage_t<DIM, LIM_VANALBADA, TX, TY, KC, FLUX>(a, grid, s);
+  }
+}
+
+template <int DIM, int TX, int TY, int KC>
+static hipError_t launch_stage_flux(int flux, int lim, const StageArgs& a, int grid, hipStream_t s) {
+  switch (flux) {
+    case FLUX_VANLEER_FVS: return launch_stage_lim<DIM, TX, TY, KC, FLUX_VANLEER_FVS>(lim, a, grid, s);
+    case FLUX_STEGER_WARMING: return launch_stage_lim<DIM, TX, TY, KC, FLUX_STEGER_WARMING>(lim, a, grid, s);
+    default: return launch_stage_lim<DIM, TX, TY, KC, FLUX_ROE>(lim, a, grid, s);
   }
 }
 
@@ -369,18 +378,18 @@ const StageVariant* stage_variants(int dim, int* count) {
   return dim == 2 ? v2 : v3;
 }
 
-hipError_t launch_stage(int dim, int lim, int variant, const StageArgs& a, int grid, hipStream_t s) {
+hipError_t launch_stage(int dim, int flux, int lim, int variant, const StageArgs& a, int grid, hipStream_t s) {
   if (dim == 2) {
     switch (variant) {
-      case 0: return launch_stage_lim<2, 64, 4, 1>(lim, a, grid, s);
-      case 1: return launch_stage_lim<2, 32, 8, 1>(lim, a, grid, s);
-      default: return launch_stage_lim<2, 16, 16, 1>(lim, a, grid, s);
+      case 0: return launch_stage_flux<2, 64, 4, 1>(flux, lim, a, grid, s);
+      case 1: return launch_stage_flux<2, 32, 8, 1>(flux, lim, a, grid, s);
+      default: return launch_stage_flux<2, 16, 16, 1>(flux, lim, a, grid, s);
     }
   }
   switch (variant) {
-    case 0: return launch_stage_lim<3, 64, 4, 32>(lim, a, grid, s);
-    case 1: return launch_stage_lim<3, 32, 8, 32>(lim, a, grid, s);
-    default: return launch_stage_lim<3, 32, 8, 64>(lim, a, grid, s);
+    case 0: return launch_stage_flux<3, 64, 4, 32>(flux, lim, a, grid, s);
+    case 1: return launch_stage_flux<3, 32, 8, 32>(flux, lim, a, grid, s);
+    default: return launch_stage_flux<3, 32, 8, 64>(flux, lim, a, grid, s);
   }
 }
 

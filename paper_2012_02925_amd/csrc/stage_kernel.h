@@ -8,9 +8,10 @@
 //   2. the limited slopes of eq. (flux) (slope form; one per cell and
 //      direction for the symmetric limiters, a high-face/low-face pair without
 //      a limiter) are computed once per cell into LDS;
-//   3. the Roe flux is computed once per i- and j-face of the tile (faces on
-//      the tile edge are shared with the neighbour tile), the wall override of
-//      Sec. 7.2 V7 applied on slip-wall faces, and stored in LDS;
+//   3. the face flux (Roe, or a flux-vector splitting) is computed once per
+//      i- and j-face of the tile (faces on the tile edge are shared with the
+//      neighbour tile), the wall override of Sec. 7.2 V7 applied on slip-wall
+//      faces, and stored in LDS;
 //   4. every cell sums its face fluxes, scales by its inverse volume and either
 //      writes the residual or applies the stage update
 //      Q^(k) = Q^(0) - alpha dt R(Q^(k-1)) (Sec. 2, M-stage Runge-Kutta) and
@@ -102,7 +103,7 @@ constexpr int stage_waves() {
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-template <int DIM, int LIM, int TX, int TY, int KC>
+template <int DIM, int LIM, int TX, int TY, int KC, int FLUX>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, LIM, TX, TY>())))
 stage_kernel(StageArgs a) {
   constexpr int NV = DIM + 2;
@@ -237,7 +238,7 @@ stage_kernel(StageArgs a) {
             else
               R[v] = qn[v] - he * snp[v];
           }
-          roe_flux<3>(L, R, Sz, a.gas, a.efix, a.half_inv_efix, F);
+          face_flux<3, FLUX>(L, R, Sz, a.gas, a.efix, a.half_inv_efix, F);
         }
       }
       pprev = qcur[NV - 1];
@@ -371,7 +372,7 @@ stage_kernel(StageArgs a) {
             L[v] = sq[v][own_lp - 1] + he * slx[0][v][ty * SXW + tx];
             R[v] = sq[v][own_lp] - he * slx[NS - 1][v][ty * SXW + tx + 1];
           }
-          roe_flux<DIM>(L, R, Sx, a.gas, a.efix, a.half_inv_efix, F);
+          face_flux<DIM, FLUX>(L, R, Sx, a.gas, a.efix, a.half_inv_efix, F);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) flx[v][ty * FXW + tx] = F[v];
@@ -389,7 +390,7 @@ stage_kernel(StageArgs a) {
             L[v] = sq[v][own_lp - LX] + he * sly[0][v][ty * TX + tx];
             R[v] = sq[v][own_lp] - he * sly[NS - 1][v][(ty + 1) * TX + tx];
           }
-          roe_flux<DIM>(L, R, Sy, a.gas, a.efix, a.half_inv_efix, F);
+          face_flux<DIM, FLUX>(L, R, Sy, a.gas, a.efix, a.half_inv_efix, F);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) fly[v][ty * TX + tx] = F[v];
@@ -437,7 +438,7 @@ stage_kernel(StageArgs a) {
               L[v] = sq[v][pL] + he * (isx ? slx[0][v][sL] : sly[0][v][sL]);
               R[v] = sq[v][pL + st] - he * (isx ? slx[NS - 1][v][sR] : sly[NS - 1][v][sR]);
             }
-            roe_flux<DIM>(L, R, S, a.gas, a.efix, a.half_inv_efix, F);
+            face_flux<DIM, FLUX>(L, R, S, a.gas, a.efix, a.half_inv_efix, F);
           }
 #pragma unroll
           for (int v = 0; v < NV; ++v) {

@@ -26,6 +26,7 @@ def config_from_scheme(dim, scheme):
         cfg.lim_eps[v] = float(le[v]) if v < len(le) else 0.0
     cfg.efix = scheme.efix
     cfg.rk_stages = scheme.rk_stages
+    cfg.flux = capi.FLUX[getattr(scheme, "flux", "roe")]
     if scheme.dt_fixed is not None:
         cfg.dt_mode = capi.DT_FIXED
         cfg.dt_fixed = float(scheme.dt_fixed)

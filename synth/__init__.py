@@ -90,6 +90,7 @@ class Scheme:
     # van Albada regularisation epsilon per primitive variable (rho, u, v[, w], p)
     lim_eps: Optional[Sequence[float]] = None
     efix: float = 0.1  # Harten smoothing width as a fraction of the Roe-averaged sound speed
+    flux: str = "roe"  # "roe" | "vanleer_fvs" | "steger_warming"
     rk_stages: int = 4
     cfl: float = 0.5
     dt_fixed: Optional[float] = None  # None = global CFL time step recomputed every step

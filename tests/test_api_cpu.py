@@ -84,6 +84,26 @@ def test_config_validation():
     assert lib.cfd_create(ctypes.byref(_cfg(capi, limiter=7)), None, ctypes.byref(ctx)) == -1
 
 
+def test_flux_selection_validation():
+    capi, lib = _lib()
+    ctx = ctypes.c_void_p()
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, flux=3)), None, ctypes.byref(ctx)) == -1
+    # the residual VJP is implemented for the Roe flux only
+    ctx = _ctx(capi, lib, flux=capi.FLUX["vanleer_fvs"])
+    _add(capi, lib, ctx, 8, 6)
+    _periodic(capi, lib, ctx, 0, 8, 6)
+    assert lib.cfd_enable_adjoint(ctx, 1) == 0
+    n = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == -7
+    assert b"Roe" in lib.cfd_last_error(ctx)
+    lib.cfd_destroy(ctx)
+    ctx = _ctx(capi, lib, flux=capi.FLUX["steger_warming"])
+    _add(capi, lib, ctx, 8, 6)
+    _periodic(capi, lib, ctx, 0, 8, 6)
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == 0
+    lib.cfd_destroy(ctx)
+
+
 def test_planning_and_workspace_size():
     capi, lib = _lib()
     ctx = _ctx(capi, lib)

@@ -102,6 +102,52 @@ def test_box3d_reduced_residual_and_steps():
     assert ok, rep
 
 
+FVS = ["vanleer_fvs", "steger_warming"]
+
+
+def _with_flux(case, flux):
+    case.scheme.flux = flux
+    case.name = case.name + "_" + flux
+    return case
+
+
+@pytest.mark.parametrize("flux", FVS)
+@pytest.mark.parametrize("lim", ["vanleer", "none"])
+def test_fvs_bump_residual_all_variants_and_steps(flux, lim):
+    _say("case: gaussian bump 64x64", flux, lim)
+    case = _with_flux(synth.gaussian_bump_periodic(64, 64, seed=2, limiter=lim), flux)
+    s = check_residual(case)
+    Qref, dts = oracle_run(case, 20)
+    s.rk_step(20)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    assert ok, rep
+
+
+@pytest.mark.parametrize("flux", FVS)
+def test_fvs_ramp_reduced_residual_and_steps(flux):
+    """Mach 2.5 inflow (van Leer's supersonic branches), subsonic pockets
+    behind the shock and slip-wall faces."""
+    _say("case: ramp 100x70", flux)
+    case = _with_flux(synth.compression_ramp(100, 70), flux)
+    s = check_residual(case)
+    s.set_variant(1)
+    Qref, dts = oracle_run(case, 30)
+    s.rk_step(30)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    assert ok, rep
+
+
+@pytest.mark.parametrize("flux", FVS)
+def test_fvs_box3d_reduced_residual_and_steps(flux):
+    _say("case: jittered box 40x36x34", flux)
+    case = _with_flux(synth.jittered_periodic_box(dims=(40, 36, 34), seed=6), flux)
+    s = check_residual(case)
+    Qref, dts = oracle_run(case, 4)
+    s.rk_step(4)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    assert ok, rep
+
+
 def test_box3d_ghost_fill():
     case = synth.jittered_periodic_box(dims=(20, 18, 17), seed=5)
     s = _solver(case)
