@@ -65,7 +65,12 @@ enum { CFD_LIM_NONE = 0, CFD_LIM_VANLEER = 1, CFD_LIM_VANALBADA = 2 };
  * STEGER_WARMING: the same with F+- = R diag((l +- |l|)/2) R^-1 Q (closed form). */
 enum { CFD_FLUX_ROE = 0, CFD_FLUX_VANLEER_FVS = 1, CFD_FLUX_STEGER_WARMING = 2 };
 enum { CFD_BC_SLIP_WALL = 1, CFD_BC_SUP_INFLOW = 2, CFD_BC_EXTRAP_OUTFLOW = 3 };
-enum { CFD_DT_CFL = 0, CFD_DT_FIXED = 1 };
+/* CFL: one global step CFL * min(Omega/lambda) from Q^n each step.  FIXED:
+ * dt_fixed.  LOCAL: every cell advances with its own CFL * Omega/lambda from
+ * Q^n (steady-state acceleration; time-inaccurate by design).
+ * lambda = sum_d |u . Sbar_d| + c |Sbar_d|, Sbar_d the mean of the cell's two
+ * area vectors in direction d. */
+enum { CFD_DT_CFL = 0, CFD_DT_FIXED = 1, CFD_DT_LOCAL = 2 };
 /* execution modes for cfd_set_exec */
 enum { CFD_EXEC_BATCHED = 0, CFD_EXEC_PER_BLOCK = 1 };
 
@@ -79,8 +84,8 @@ typedef struct {
   double lim_eps[5];    /* van Albada regularisation per primitive variable (rho,u,v[,w],p) */
   double efix;          /* Harten smoothing half-width as a fraction of the Roe sound speed; 0 = off */
   int rk_stages;        /* M of the M-stage scheme, alpha_k = 1/(M-k+1); 1..8 */
-  int dt_mode;          /* CFD_DT_CFL: global CFL step from Q^n each step; CFD_DT_FIXED */
-  double cfl;           /* CFL number for CFD_DT_CFL */
+  int dt_mode;          /* CFD_DT_CFL | CFD_DT_FIXED | CFD_DT_LOCAL */
+  double cfl;           /* CFL number for CFD_DT_CFL and CFD_DT_LOCAL */
   double dt_fixed;      /* time step for CFD_DT_FIXED */
   int flux;             /* CFD_FLUX_*: inviscid face flux (Sec. 2 lists Roe's flux-difference
                            splitting and van Leer's and Steger-Warming's flux-vector
@@ -152,11 +157,19 @@ cfd_status cfd_get_state(cfd_ctx* ctx, double* dev_Q);
 
 /* Residual R(Q) of the current state, packed conservative layout, with
  * dQ/dt = -R: ghost fill (connections, then physical patches), MUSCL face
- * states, Roe flux on every face, wall-flux override, flux divergence / volume. */
+ * states, the configured face flux on every face, wall-flux override, flux
+ * divergence / volume. */
 cfd_status cfd_residual(cfd_ctx* ctx, double* dev_R);
 
+/* cfd_residual into dev_R, plus dev_norms[v] = sqrt(sum over all cells of
+ * R_v^2 / ncells) for each conservative variable v (nvar doubles, device
+ * memory): the convergence monitor of steady runs (divide by the first
+ * iteration's norms for the relative history).  Deterministic: fixed
+ * partition of the cells and fixed reduction order. */
+cfd_status cfd_residual_norms(cfd_ctx* ctx, double* dev_R, double* dev_norms);
+
 /* Global CFL time step CFL * min(Omega / lambda) of the current state, or the
- * fixed step, written to dev_dt[0]. */
+ * fixed step, written to dev_dt[0]; with CFD_DT_LOCAL the smallest cell step. */
 cfd_status cfd_time_step(cfd_ctx* ctx, double* dev_dt);
 
 /* Advance nsteps M-stage Runge-Kutta steps in place.  The time step of each

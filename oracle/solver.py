@@ -54,6 +54,7 @@ class Problem:
         self.stages = sch.rk_stages
         self.cfl = sch.cfl
         self.dt_fixed = sch.dt_fixed
+        self.local_dt = getattr(sch, "local_dt", False)
         le = sch.lim_eps if sch.lim_eps is not None else [0.0] * self.nvar
         self.lim_eps2 = torch.tensor([e * e for e in le], dtype=F64)
         self.nodes = [torch.tensor(b.nodes, dtype=F64, requires_grad=requires_grad) for b in case.blocks]
@@ -165,10 +166,23 @@ class Problem:
         m = min(self.cell_dt(Q, met[b][0], met[b][1]).min() for b, Q in enumerate(Q_list))
         return self.cfl * m
 
+    def local_steps(self, Q_list, met=None):
+        """Local time stepping (steady-state acceleration): every cell advances
+        with its own dt_i = CFL * Omega_i / lambda_i from Q^n."""
+        met = self.metrics() if met is None else met
+        return [self.cfl * self.cell_dt(Q, met[b][0], met[b][1]) for b, Q in enumerate(Q_list)]
+
     # -- Runge-Kutta --------------------------------------------------------
     def rk_step(self, Q_list, met=None, dt=None, residual_fn=None):
+        """One M-stage step.  Returns the new state and the step: the global
+        dt, or with local stepping the smallest cell step."""
         met = self.metrics() if met is None else met
-        dt = self.time_step(Q_list, met) if dt is None else dt
+        if self.local_dt and dt is None:
+            dts = self.local_steps(Q_list, met)
+            dt = min(d.min() for d in dts)
+        else:
+            dt = self.time_step(Q_list, met) if dt is None else dt
+            dts = [dt] * len(Q_list)
         res = (lambda Qs: self.residual(Qs, met)) if residual_fn is None else residual_fn
         M = self.stages
         Q0 = Q_list
@@ -176,8 +190,16 @@ class Problem:
         for k in range(1, M + 1):
             alpha = 1.0 / (M - k + 1)
             R = res(Qk)
-            Qk = [Q0[b] - alpha * dt * R[b] for b in range(len(Q0))]
+            Qk = [Q0[b] - alpha * dts[b] * R[b] for b in range(len(Q0))]
         return Qk, dt
+
+    def residual_norms(self, Q_list, met=None):
+        """Root-mean-square residual per conservative variable over all cells
+        (the convergence monitor of steady runs)."""
+        R = self.residual(Q_list, met)
+        n = sum(r[0].numel() for r in R)
+        ss = sum((r.reshape(self.nvar, -1) ** 2).sum(1) for r in R)
+        return torch.sqrt(ss / n)
 
     def run(self, Q_list, steps, met=None):
         met = self.metrics() if met is None else met

@@ -15,7 +15,7 @@ STATUS = {0: "CFD_OK", -1: "CFD_ERR_ARG", -2: "CFD_ERR_STATE", -3: "CFD_ERR_TOPO
 LIM = {"none": 0, "vanleer": 1, "vanalbada": 2}
 FLUX = {"roe": 0, "vanleer_fvs": 1, "steger_warming": 2}
 BC = {"slip_wall": 1, "sup_inflow": 2, "extrap_outflow": 3}
-DT_CFL, DT_FIXED = 0, 1
+DT_CFL, DT_FIXED, DT_LOCAL = 0, 1, 2
 EXEC_BATCHED, EXEC_PER_BLOCK = 0, 1
 Q = {"nblocks": 0, "ncells": 1, "nvar": 2, "nvariants": 3, "variant": 4, "ntiles": 5, "ntransfers": 6,
      "npatches": 7, "nnodes": 8, "exchange_doubles": 9, "workspace_bytes": 10, "tile_x": 11, "tile_y": 12}
@@ -72,6 +72,7 @@ SIGNATURES = {
     "cfd_residual_vjp": ([_P, _P, _P, _P, _P], _I),
     "cfd_adjoint_reset": ([_P], _I),
     "cfd_rk_step_vjp": ([_P, _P], _I),
+    "cfd_residual_norms": ([_P, _P, _P], _I),
     "cfd_rk_step_record": ([_P, _P], _I),
     "cfd_rk_step_vjp_recorded": ([_P, _P, _P], _I),
     "cfd_objective_wall_pressure": ([_P, _P, _P], _I),

@@ -106,6 +106,8 @@ struct cfd_ctx {
   std::vector<int> inflow_list, wall_list;
   long long part_doubles = 0;
   static constexpr int SUM_PARTS = 1024;
+  static constexpr int NORM_PARTS = 1024;
+  size_t off_dtloc = 0, off_normpart = 0;
 
   // timing
   bool profiling = false;
@@ -220,9 +222,10 @@ extern "C" cfd_status cfd_create(const cfd_config* cfg, void* stream, cfd_ctx** 
   if (cfg->limiter < CFD_LIM_NONE || cfg->limiter > CFD_LIM_VANALBADA) return CFD_ERR_ARG;
   if (cfg->flux < CFD_FLUX_ROE || cfg->flux > CFD_FLUX_STEGER_WARMING) return CFD_ERR_ARG;
   if (cfg->rk_stages < 1 || cfg->rk_stages > 8) return CFD_ERR_ARG;
-  if (cfg->dt_mode == CFD_DT_CFL && !(cfg->cfl > 0.0)) return CFD_ERR_ARG;
+  if ((cfg->dt_mode == CFD_DT_CFL || cfg->dt_mode == CFD_DT_LOCAL) && !(cfg->cfl > 0.0)) return CFD_ERR_ARG;
   if (cfg->dt_mode == CFD_DT_FIXED && !(cfg->dt_fixed > 0.0)) return CFD_ERR_ARG;
-  if (cfg->dt_mode != CFD_DT_CFL && cfg->dt_mode != CFD_DT_FIXED) return CFD_ERR_ARG;
+  if (cfg->dt_mode != CFD_DT_CFL && cfg->dt_mode != CFD_DT_FIXED && cfg->dt_mode != CFD_DT_LOCAL)
+    return CFD_ERR_ARG;
   if (!(cfg->efix >= 0.0) || !(cfg->muscl_eps >= 0.0)) return CFD_ERR_ARG;
   for (int v = 0; v < MAXV; ++v)
     if (!(cfg->lim_eps[v] >= 0.0)) return CFD_ERR_ARG;
@@ -559,6 +562,8 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->off_dt = take(2 * 8);
   c->off_dtmin = take(8);
   c->off_err = take(4);
+  c->off_normpart = take((size_t)cfd_ctx::NORM_PARTS * MAXV * 8);
+  if (c->cfg.dt_mode == CFD_DT_LOCAL) c->off_dtloc = take((size_t)c->ncells * 8);
   c->off_blocks = take(c->blocks.size() * sizeof(BlockDev));
   c->off_xfers = take(c->xfers.size() * sizeof(TransferDev));
   c->off_patches = take(c->patches.size() * sizeof(PatchDev));
@@ -798,6 +803,8 @@ static StageArgs stage_args(cfd_ctx* c) {
   a.efix = c->cfg.efix;
   a.half_inv_efix = c->cfg.efix > 0.0 ? 0.5 / c->cfg.efix : 0.0;
   for (int v = 0; v < MAXV; ++v) a.e2[v] = c->cfg.lim_eps[v] * c->cfg.lim_eps[v];
+  a.dtloc = c->cfg.dt_mode == CFD_DT_LOCAL ? c->dptr<double>(c->off_dtloc) : nullptr;
+  a.cfl = c->cfg.cfl;
   return a;
 }
 
@@ -866,7 +873,7 @@ static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool 
 
 // Enqueue one full Runge-Kutta step on stream s.
 static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
-  const bool cfl = c->cfg.dt_mode == CFD_DT_CFL;
+  const bool cfl = c->cfg.dt_mode != CFD_DT_FIXED;
   if (cfl)
     HIP_TRY(c, launch_dt_promote(c->dptr<double>(c->off_dt), c->dptr<unsigned long long>(c->off_dtmin), c->cfg.cfl, 1,
                                  nullptr, s));
@@ -894,10 +901,14 @@ static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
 }
 
 static cfd_status ensure_dt(cfd_ctx* c) {
-  if (c->cfg.dt_mode != CFD_DT_CFL || c->dt_valid) return CFD_OK;
+  if (c->cfg.dt_mode == CFD_DT_FIXED || c->dt_valid) return CFD_OK;
   HIP_TRY(c, launch_set_u64(c->dptr<unsigned long long>(c->off_dtmin), 0x7ff0000000000000ULL, c->stream));
   CellArgs a = cell_args(c);
   a.src = c->stA();
+  if (c->cfg.dt_mode == CFD_DT_LOCAL) {
+    a.dtloc = c->dptr<double>(c->off_dtloc);
+    a.cfl = c->cfg.cfl;
+  }
   HIP_TRY(c, launch_cell_dt(c->dim, a, c->max_cells, (int)c->blocks.size(), c->stream));
   c->dt_valid = true;
   return CFD_OK;
@@ -970,6 +981,15 @@ extern "C" cfd_status cfd_residual(cfd_ctx* c, double* dev_R) {
   a.Rout = dev_R;
   a.mode = MODE_RESIDUAL;
   return launch_stage_all(c, a, c->stream, false);
+}
+
+extern "C" cfd_status cfd_residual_norms(cfd_ctx* c, double* dev_R, double* dev_norms) {
+  if (!dev_norms) return CFD_ERR_ARG;
+  cfd_status s = cfd_residual(c, dev_R);
+  if (s != CFD_OK) return s;
+  const int parts = (int)std::min<long long>(cfd_ctx::NORM_PARTS, std::max<long long>(1, c->ncells / 4096));
+  HIP_TRY(c, launch_sumsq(c->nvar, dev_R, c->ncells, c->dptr<double>(c->off_normpart), parts, dev_norms, c->stream));
+  return CFD_OK;
 }
 
 extern "C" cfd_status cfd_time_step(cfd_ctx* c, double* dev_dt) {
@@ -1303,7 +1323,7 @@ extern "C" cfd_status cfd_rk_step_record(cfd_ctx* c, void* dev_stages) {
   if (!dev_stages) return CFD_ERR_ARG;
   if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
   if ((s = ensure_dt(c)) != CFD_OK) return s;
-  const bool cfl = c->cfg.dt_mode == CFD_DT_CFL;
+  const bool cfl = c->cfg.dt_mode != CFD_DT_FIXED;
   hipStream_t hs = c->stream;
   if (cfl)
     HIP_TRY(c, launch_dt_promote(c->dptr<double>(c->off_dt), c->dptr<unsigned long long>(c->off_dtmin), c->cfg.cfl,

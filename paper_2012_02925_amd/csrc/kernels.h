@@ -29,6 +29,8 @@ struct CellArgs {
   const double* metric;
   const long long* offsets;  // export_padded: output offset per block
   unsigned long long* dtmin;
+  double* dtloc;  // non-null: also write cfl * Omega/lambda per cell (packed)
+  double cfl;
   int* err;
   int flag_primitive;
   Gas gas;
@@ -46,6 +48,8 @@ struct StageVariant {
 };
 
 const StageVariant* stage_variants(int dim, int* count);
+hipError_t launch_sumsq(int nvar, const double* R, long long ncells, double* partial, int nparts,
+                        double* norms, hipStream_t s);
 hipError_t launch_stage(int dim, int flux, int lim, int variant, const StageArgs& a, int grid, hipStream_t s);
 hipError_t launch_ghost(int dim, const GhostArgs& a, int nchunks, hipStream_t s);
 hipError_t launch_set_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);

@@ -192,6 +192,7 @@ __global__ void __launch_bounds__(256) cell_dt_kernel(CellArgs a) {
       lam += fabs(un) + cs * sqrt(s2);
     }
     m = 1.0 / (lam * met[ML::INVVOL * vs]);
+    if (a.dtloc) a.dtloc[B.packed + c] = a.cfl * m;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
@@ -341,6 +342,60 @@ __global__ void export_padded_kernel(CellArgs a) {
   double* dst = a.dst + a.offsets[blockIdx.y];
 #pragma unroll
   for (int v = 0; v < NV; ++v) dst[v * n + c] = src[v * B.vstride];
+}
+
+// ---------------------------------------------------------------------------
+// residual norms: per-part sums of squares over fixed contiguous cell ranges,
+// then one workgroup adds the parts in order
+
+template <int NV>
+__global__ void __launch_bounds__(256) sumsq_partial_kernel(const double* R, long long ncells, double* partial) {
+  __shared__ double red[256];
+  const long long per = (ncells + gridDim.x - 1) / gridDim.x;
+  const long long lo = (long long)blockIdx.x * per;
+  const long long hi = min(ncells, lo + per);
+  for (int v = 0; v < NV; ++v) {
+    double s = 0.0;
+    for (long long c = lo + threadIdx.x; c < hi; c += blockDim.x) s += R[v * ncells + c] * R[v * ncells + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long long)v * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+template <int NV>
+__global__ void __launch_bounds__(256) norms_kernel(const double* partial, int nparts, long long ncells,
+                                                    double* norms) {
+  __shared__ double red[256];
+  for (int v = 0; v < NV; ++v) {
+    double s = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += partial[(long long)v * nparts + p];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) norms[v] = sqrt(red[0] / (double)ncells);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sumsq(int nvar, const double* R, long long ncells, double* partial, int nparts,
+                        double* norms, hipStream_t s) {
+  if (nvar == 4) {
+    hipLaunchKernelGGL(sumsq_partial_kernel<4>, dim3(nparts), dim3(256), 0, s, R, ncells, partial);
+    hipLaunchKernelGGL(norms_kernel<4>, dim3(1), dim3(256), 0, s, partial, nparts, ncells, norms);
+  } else {
+    hipLaunchKernelGGL(sumsq_partial_kernel<5>, dim3(nparts), dim3(256), 0, s, R, ncells, partial);
+    hipLaunchKernelGGL(norms_kernel<5>, dim3(1), dim3(256), 0, s, partial, nparts, ncells, norms);
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -48,6 +48,9 @@ struct StageArgs {
   double alpha;
   int mode;
   unsigned long long* dtmin;  // non-null: reduce Omega/lambda of the new state (bits of a positive double)
+  double* dtloc;         // non-null: local time steps, packed per cell; read for the update and, with
+                         // dtmin, overwritten by cfl * Omega/lambda of the new state
+  double cfl;
   Gas gas;
   double half_eps;       // muscl eps / 2
   double kappa;          // muscl kappa (used only without a limiter)
@@ -449,10 +452,13 @@ stage_kernel(StageArgs a) {
           }
         }
       }
-      // inverse volume and stage-start state, consumed after the next barrier
-      double iv = 0.0, w0[NV];
+      // inverse volume, stage-start state and (local stepping) the cell's time
+      // step, consumed after the next barrier
+      double iv = 0.0, w0[NV], adtc = adt;
+      const long long pcell = B.packed + ((long long)k * B.nj + j) * B.ni + i;
       if (own) {
         iv = ld_at(met + ML::INVVOL * vs, ok);
+        if (update && a.dtloc) adtc = a.alpha * a.dtloc[pcell];
         if (update && !q0_is_qin) {
           const double* q0 = a.q0 + (B.origin - K);
 #pragma unroll
@@ -492,9 +498,8 @@ stage_kernel(StageArgs a) {
           R[v] = div * iv;
         }
         if (!update) {
-          const long long pc = B.packed + ((long long)k * B.nj + j) * B.ni + i;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) a.Rout[v * B.ncell_total + pc] = R[v];
+          for (int v = 0; v < NV; ++v) a.Rout[v * B.ncell_total + pcell] = R[v];
         } else {
           double Q[NV], qnew[NV];
           if (q0_is_qin) {
@@ -503,7 +508,7 @@ stage_kernel(StageArgs a) {
           }
           prim_to_cons<DIM>(w0, a.gas, Q);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) Q[v] -= adt * R[v];
+          for (int v = 0; v < NV; ++v) Q[v] -= adtc * R[v];
           cons_to_prim<DIM>(Q, a.gas, qnew);
           double* qo = a.qout + (B.origin - K);
 #pragma unroll
@@ -525,7 +530,9 @@ stage_kernel(StageArgs a) {
               }
               lam += fabs(un) + c * sqrt(s2);
             }
-            my_min = fmin(my_min, 1.0 / (lam * iv));
+            const double om = 1.0 / (lam * iv);
+            my_min = fmin(my_min, om);
+            if (a.dtloc) a.dtloc[pcell] = a.cfl * om;
           }
         }
       }

@@ -30,6 +30,9 @@ def config_from_scheme(dim, scheme):
     if scheme.dt_fixed is not None:
         cfg.dt_mode = capi.DT_FIXED
         cfg.dt_fixed = float(scheme.dt_fixed)
+    elif getattr(scheme, "local_dt", False):
+        cfg.dt_mode = capi.DT_LOCAL
+        cfg.cfl = scheme.cfl
     else:
         cfg.dt_mode = capi.DT_CFL
         cfg.cfl = scheme.cfl
@@ -140,6 +143,13 @@ class Solver:
         R = torch.empty((self.nvar, self.ncells), dtype=F64, device=self.device) if out is None else out
         self._check(self.lib.cfd_residual(self.ctx, dptr(R)))
         return R
+
+    def residual_norms(self):
+        """(R, per-variable RMS norms of R) at the current state."""
+        R = torch.empty((self.nvar, self.ncells), dtype=F64, device=self.device)
+        N = torch.empty(self.nvar, dtype=F64, device=self.device)
+        self._check(self.lib.cfd_residual_norms(self.ctx, dptr(R), dptr(N)))
+        return R, N
 
     def time_step(self):
         dt = torch.empty(1, dtype=F64, device=self.device)

@@ -94,6 +94,7 @@ class Scheme:
     rk_stages: int = 4
     cfl: float = 0.5
     dt_fixed: Optional[float] = None  # None = global CFL time step recomputed every step
+    local_dt: bool = False  # local time stepping: every cell with its own CFL step (steady runs)
 
 
 @dataclasses.dataclass

@@ -200,3 +200,35 @@ def test_variants_are_bitwise_identical_3d():
             _say("variant", v, "max diff", float(d.max()), "at cell (i,j,k) =",
                  (flat % ni, (flat // ni) % nj, flat // (ni * nj)), "count", int((d > 0).sum()))
         assert torch.equal(o, outs[0])
+
+
+def test_local_time_stepping_ramp():
+    """Local time stepping (every cell with its own CFL step from Q^n) on the
+    reduced ramp: state after 25 steps and the reported smallest step."""
+    _say("case: ramp 100x70, local time stepping, 25 steps")
+    case = synth.compression_ramp(100, 70)
+    case.scheme.local_dt = True
+    s = _solver(case)
+    Qref, dts = oracle_run(case, 25)
+    dt_last = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    s.rk_step(25, dt_last)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    assert ok, rep
+    assert abs(dt_last.item() - dts[-1]) <= 1e-12 * dts[-1]
+
+
+@pytest.mark.parametrize("dims", [(64, 64, 1), (40, 36, 34)])
+def test_residual_norms(dims):
+    import oracle
+    case = (synth.gaussian_bump_periodic(dims[0], dims[1], seed=5) if dims[2] == 1
+            else synth.jittered_periodic_box(dims=dims, seed=7))
+    s = _solver(case)
+    R, N = s.residual_norms()
+    P = oracle.Problem(case)
+    Nref = P.residual_norms(P.initial_state())
+    # components whose residual is rounding-level (the bump's y-momentum)
+    # are bounded like the residual itself: 1e-12 of the reference flux scale
+    err = (N.cpu() - Nref).abs()
+    bound = 1e-11 * Nref + 1e-12 * torch.as_tensor(residual_scale(case, q_ref(case)), dtype=torch.float64)
+    _say("  norms", N.cpu().tolist(), "err", err.tolist())
+    assert (err <= bound).all(), (err, bound)

@@ -305,3 +305,62 @@ def test_oblique_shock_plateau():
     # and the free stream ahead of the shock is untouched
     ahead = (yc > (xc - 0.5).clamp(min=0) * math.tan(beta) + 0.2)
     assert (q[3][ahead] / (1 / 1.4) - 1).abs().max() < 1e-6
+
+
+# -- local time stepping and residual norms ------------------------------------
+
+def test_local_stepping_equals_global_for_uniform_cell_steps():
+    """On a uniform Cartesian periodic grid with uniform velocity and sound
+    speed every cell has the same Omega/lambda, so local and global stepping
+    take the same step and give the same state."""
+    c = synth.gaussian_bump_periodic(16, 12, seed=3)
+    # uniform u and p: every cell has the same sound speed and Omega/lambda
+    # (up to the rounding of the node-based metrics)
+    c = uniform(c, [1.0, 0.5, 0.0, 1 / 1.4])
+    c.prims[0][0] *= 1.0 + 0.01 * np.sin(np.arange(16) * 0.7)[None, :]
+    c.prims[0][3] = c.prims[0][0] / 1.4  # constant temperature: uniform c
+    Pg = Problem(c)
+    cl = copy.deepcopy(c)
+    cl.scheme.local_dt = True
+    Pl = Problem(cl)
+    Q = Pg.initial_state()
+    met = Pg.metrics()
+    dl = Pl.local_steps(Q, met)[0]
+    dg = float(Pg.time_step(Q, met))
+    assert (dl - dg).abs().max() <= 1e-15 * dg
+    Qg, dtg = Pg.rk_step(Q, met)
+    Ql, dtl = Pl.rk_step(Q, met)
+    assert (Qg[0] - Ql[0]).abs().max() <= 1e-14 and abs(float(dtg) - float(dtl)) <= 1e-15 * dg
+    # and a state whose cells have different steps moves differently
+    c2 = copy.deepcopy(c)
+    c2.prims[0][3] = np.full_like(c2.prims[0][3], 1 / 1.4)
+    P2g, P2l = Problem(c2), Problem(copy.deepcopy(cl))
+    P2l.case.prims[0] = c2.prims[0]
+    Q2 = P2g.initial_state()
+    assert (P2g.rk_step(Q2, met)[0][0] - P2l.rk_step(Q2, met)[0][0]).abs().max() > 1e-9
+
+
+def test_local_steps_follow_cell_size():
+    """Cartesian closed form per cell: dt_i = CFL h_x h_y / (|u| h_y + c h_y + c h_x)
+    with different spacings in the two halves of a stretched grid."""
+    c = synth.compression_ramp(12, 8)
+    c.blocks[0].nodes = synth.cartesian_nodes_2d(12, 8, lx=1.5)
+    c.scheme.local_dt = True
+    P = Problem(c)
+    Q = P.initial_state()
+    dts = P.local_steps(Q)[0]
+    hx, hy = 1.5 / 12, 1.0 / 8
+    u, cs = 2.5, 1.0
+    ref = 0.5 * hx * hy / ((u + cs) * hy + cs * hx)
+    assert (dts - ref).abs().max() <= 1e-15
+
+
+def test_residual_norms_are_rms_per_variable():
+    c = synth.jittered_periodic_square(10, 8, seed=6)
+    P = Problem(c)
+    Q = P.initial_state()
+    N = P.residual_norms(Q)
+    R = P.residual(Q)[0].reshape(4, -1)
+    for v in range(4):
+        ref = math.sqrt(sum(float(x) ** 2 for x in R[v]) / R.shape[1])
+        assert abs(float(N[v]) - ref) <= 1e-14 * ref
