@@ -14,7 +14,9 @@ Readings (the paper names the boundary types but prints no formulas):
   * slip wall: ghost layer g mirrors interior layer g: rho and p copied,
     velocity reflected about the wall face, u - 2 (u . n) n;
   * supersonic inflow: both ghost layers hold the inflow primitive state;
-  * extrapolated outflow: both ghost layers copy the adjacent interior cell.
+  * extrapolated outflow: both ghost layers copy the adjacent interior cell;
+  * farfield, subsonic inflow, subsonic outflow: both ghost layers hold the
+    characteristic boundary state of oracle/bc.py.
 Corner ghosts are not filled; the dimension-by-dimension stencil never reads them.
 
 Arrays: interior primitive state ``q`` (nvar, [nk,] nj, ni); padded state
@@ -22,6 +24,8 @@ Arrays: interior primitive state ``q`` (nvar, [nk,] nj, ni); padded state
 axis ``q.ndim - 1 - a``.
 """
 import torch
+
+from . import bc
 
 
 def tensor_axis(ndim, logical_axis):
@@ -146,10 +150,33 @@ def fill_ghosts(problem, q_list, S_list):
                 theta = problem.bc_params[p.index]
                 ref = interior_layer(q, dim, p.face, 0, p.lo, p.hi)
                 vals = theta.reshape([-1] + [1] * (ref.ndim - 1)).expand_as(ref)
+            elif p.kind in ("farfield", "sub_inflow", "sub_outflow"):
+                vals = boundary_state(problem, p, q, S_list[p.block])
             else:
                 raise ValueError(p.kind)
             set_ghost_layer(pads[p.block], dim, p.face, g, p.lo, p.hi, vals)
     return pads
+
+
+def outward_normal(S_list_block, dim, face, lo, hi):
+    """Unit outward normal (dim, t1[, t2]) of a block face over the range (the
+    stored area vectors point towards increasing index)."""
+    Sf = face_area_slab(S_list_block[face // 2], dim, face, lo, hi)
+    n = Sf / torch.sqrt((Sf * Sf).sum(0))
+    return -n if face % 2 == 0 else n
+
+
+def boundary_state(problem, p, q, S_block):
+    """Characteristic boundary state of a farfield / subsonic patch."""
+    dim, g = problem.dim, problem.gamma
+    qi = interior_layer(q, dim, p.face, 0, p.lo, p.hi)
+    prm = torch.as_tensor(p.params, dtype=qi.dtype)
+    if p.kind == "sub_inflow":
+        return bc.subsonic_inflow_state(qi, prm, g)
+    n = outward_normal(S_block, dim, p.face, p.lo, p.hi)
+    if p.kind == "farfield":
+        return bc.farfield_state(qi, n, prm, g)
+    return bc.subsonic_outflow_state(qi, n, prm[0], g)
 
 
 def _inverse_map(values_a, dim, len_b, len_a, orient):

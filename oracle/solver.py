@@ -10,6 +10,9 @@
   boundary enforcement.  Reading: F = (0, p_w S, 0) with the wall pressure
   extrapolated linearly in index space, p_w = 1.5 p_0 - 0.5 p_1 (p_0 the cell
   adjacent to the wall, p_1 the next one in).
+* Farfield faces: V7 overwrites those too.  Reading: the face flux is the
+  exact normal flux of the characteristic boundary state q_b (oracle/bc.py)
+  that the farfield ghost cells hold, F = F(q_b) . S.
 * Time step: the paper does not state it.  Reading: a global step
   dt = CFL * min over all cells of Omega / lambda, with
   lambda = sum_d (|u . Sbar_d| + c |Sbar_d|), Sbar_d the mean of the cell's
@@ -23,7 +26,7 @@ from __future__ import annotations
 import torch
 
 from . import fvs, gas, metrics as metrics_mod, muscl, roe
-from .ghosts import face_area_slab, fill_ghosts, interior_layer, tangential_axes, tensor_axis
+from .ghosts import boundary_state, face_area_slab, fill_ghosts, interior_layer, tangential_axes, tensor_axis
 
 F64 = torch.float64
 
@@ -32,6 +35,7 @@ class _Patch:
     def __init__(self, p, index):
         self.block, self.face, self.lo, self.hi, self.kind = p.block, p.face, list(p.lo), list(p.hi), p.kind
         self.index = index
+        self.params = list(p.params) if p.params is not None else None
 
 
 class Problem:
@@ -76,7 +80,10 @@ class Problem:
 
     # -- residual -----------------------------------------------------------
     def block_residual_padded(self, qpad, S, vol, walls=()):
-        """Residual of one block from a padded primitive array (ghosts given)."""
+        """Residual of one block from a padded primitive array (ghosts given).
+
+        ``walls``: boundary patches of the block whose face flux is overwritten
+        (slip walls and farfield faces), or (face, lo, hi) triples of slip walls."""
         dim = self.dim
         nd = qpad.ndim
         eps2 = self.lim_eps2.reshape([-1] + [1] * (nd - 1))
@@ -91,10 +98,14 @@ class Problem:
             qd = qpad[tuple(sl)]
             qL, qR = muscl.face_states(qd, ax, self.limiter, self.eps, self.kappa, eps2)
             F = self.face_flux(qL, qR, S[d])
-            for (face, lo, hi) in walls:
+            for w in walls:
+                face, lo, hi = (w.face, w.lo, w.hi) if isinstance(w, _Patch) else w
                 if face // 2 != d:
                     continue
-                F = self._wall_override(F, qpad, S[d], face, lo, hi)
+                if isinstance(w, _Patch) and w.kind == "farfield":
+                    F = self._farfield_override(F, qpad, S, w)
+                else:
+                    F = self._wall_override(F, qpad, S[d], face, lo, hi)
             n = F.shape[ax] - 1
             div = div + (F.narrow(ax, 1, n) - F.narrow(ax, 0, n))
         return div / vol
@@ -133,8 +144,27 @@ class Problem:
         F[tuple(sl)] = Fw
         return F
 
+    def _farfield_override(self, F, qpad, S, p):
+        dim, nd = self.dim, F.ndim
+        ax = tensor_axis(nd, p.face // 2)
+        q = qpad[tuple([slice(None)] + [slice(2, -2)] * dim)]
+        qb = boundary_state(self, p, q, S)
+        Sf = face_area_slab(S[p.face // 2], dim, p.face, p.lo, p.hi)
+        area = torch.sqrt((Sf * Sf).sum(0))
+        Fb = gas.normal_flux(qb, Sf / area, self.gamma) * area
+        sl = [slice(None)] * nd
+        sl[ax] = 0 if p.face % 2 == 0 else F.shape[ax] - 1
+        for t, a in enumerate(tangential_axes(dim, p.face)):
+            sl[tensor_axis(nd, a)] = slice(p.lo[t], p.hi[t])
+        if dim == 3:
+            Fb = Fb.permute(0, 2, 1)
+        F = F.clone()
+        F[tuple(sl)] = Fb
+        return F
+
     def walls_of(self, b):
-        return [(p.face, p.lo, p.hi) for p in self.bcs if p.block == b and p.kind == "slip_wall"]
+        """Patches of block b whose face flux is overwritten: slip walls and farfield."""
+        return [p for p in self.bcs if p.block == b and p.kind in ("slip_wall", "farfield")]
 
     def residual(self, Q_list, met=None):
         met = self.metrics() if met is None else met

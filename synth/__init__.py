@@ -38,6 +38,9 @@ IMIN, IMAX, JMIN, JMAX, KMIN, KMAX = range(6)
 SLIP_WALL = "slip_wall"
 SUP_INFLOW = "sup_inflow"
 EXTRAP_OUTFLOW = "extrap_outflow"
+FARFIELD = "farfield"  # params: free-stream primitive state
+SUB_INFLOW = "sub_inflow"  # params: (p0, rho0, direction)
+SUB_OUTFLOW = "sub_outflow"  # params: (p_back,)
 
 LIMITER_NONE = "none"
 LIMITER_VANLEER = "vanleer"
@@ -59,7 +62,7 @@ class BoundaryPatch:
     lo: Sequence[int]
     hi: Sequence[int]
     kind: str
-    params: Optional[np.ndarray] = None  # inflow primitive state (rho, u, v[, w], p)
+    params: Optional[np.ndarray] = None  # per kind: see the kind constants above
 
 
 @dataclasses.dataclass
@@ -355,6 +358,127 @@ def patchwork(seed=0, nbx=8, nby=8, side_lo=64, side_hi=512, h=1.0 / 512, mach=2
             conns.append(Connection(A, JMAX, [0], [wA], N, JMIN, [0], [wA], 0))
     return Case("patchwork_%dx%d_seed%d" % (nbx, nby, seed), 2, blocks, [], conns, prims,
                 Scheme(limiter=limiter), steps, meta={"widths": widths, "heights": heights})
+
+
+def stagnation_state(mach, gamma=GAMMA, rho=1.0, p=1.0 / GAMMA):
+    """Stagnation pressure and density of a flow at Mach ``mach`` with static
+    density ``rho`` and pressure ``p`` (isentropic relations)."""
+    f = 1.0 + 0.5 * (gamma - 1.0) * mach * mach
+    return p * f ** (gamma / (gamma - 1.0)), rho * f ** (1.0 / (gamma - 1.0))
+
+
+def _smooth_field(rng, X, Y, nmodes=3, Z=None):
+    """Sum of random low-wavenumber cosines scaled to max |f| <= 1."""
+    f = np.zeros_like(X)
+    for _ in range(nmodes):
+        k = rng.integers(1, 4, size=3)
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        arg = np.pi * (k[0] * X + k[1] * Y + (0.0 if Z is None else k[2] * Z)) + ph
+        f += np.cos(arg)
+    return f / nmodes
+
+
+def bump_channel_nodes_2d(ni, nj, length=3.0, height=1.0, bump=0.1, jitter=0.0, seed=0):
+    """Channel [0, length] x [0, height] whose lower wall carries a sin^2 bump
+    of height ``bump`` between x = length/3 and 2 length/3; nodes spread
+    uniformly between the walls, interior nodes optionally moved in index
+    space by a smooth seeded field of amplitude ``jitter`` (a fraction of the
+    domain; it vanishes on the boundary)."""
+    xi = np.linspace(0.0, 1.0, ni + 1)
+    eta = np.linspace(0.0, 1.0, nj + 1)
+    XI, ETA = np.meshgrid(xi, eta, indexing="xy")
+    if jitter:
+        rng = np.random.default_rng(seed)
+        fx = _smooth_field(rng, XI, ETA) * np.sin(np.pi * XI) * np.sin(np.pi * ETA)
+        fy = _smooth_field(rng, XI, ETA) * np.sin(np.pi * XI) * np.sin(np.pi * ETA)
+        XI = XI + jitter * fx
+        ETA = ETA + jitter * fy
+    X = length * XI
+    a, b = length / 3.0, 2.0 * length / 3.0
+    yw = np.where((X > a) & (X < b), bump * np.sin(np.pi * (X - a) / (b - a)) ** 2, 0.0)
+    Y = yw + (height - yw) * ETA
+    return np.stack([X, Y]).astype(np.float64)
+
+
+def subsonic_channel(ni=96, nj=32, mach=0.5, seed=0, amp=0.02, pressure_amp=0.0,
+                     limiter=LIMITER_VANLEER, steps=200) -> Case:
+    """2D channel with a bump on the lower wall: subsonic inflow at imin
+    (stagnation state of the Mach ``mach`` free stream, direction +x),
+    subsonic outflow at imax (back pressure 1/gamma), slip walls at jmin and
+    jmax.  Initial state: the free stream plus smooth seeded perturbations of
+    velocity (``amp`` of the free-stream speed) and pressure
+    (``pressure_amp`` of the static pressure)."""
+    nodes = bump_channel_nodes_2d(ni, nj, jitter=0.02, seed=seed)
+    blk = Block(ni, nj, 1, nodes)
+    p0, r0 = stagnation_state(mach)
+    rng = np.random.default_rng(seed + 101)
+    X, Y = cell_centres_index_space(ni, nj)
+    u = mach * (1.0 + amp * _smooth_field(rng, X, Y))
+    v = mach * amp * _smooth_field(rng, X, Y)
+    p = (1.0 + pressure_amp * _smooth_field(rng, X, Y)) / GAMMA
+    prim = np.stack([np.ones_like(X) + 0.5 * amp * _smooth_field(rng, X, Y), u, v, p])
+    bcs = [full_face_patch(2, blk, 0, IMIN, SUB_INFLOW, [p0, r0, 1.0, 0.0]),
+           full_face_patch(2, blk, 0, IMAX, SUB_OUTFLOW, [1.0 / GAMMA]),
+           full_face_patch(2, blk, 0, JMIN, SLIP_WALL),
+           full_face_patch(2, blk, 0, JMAX, SLIP_WALL)]
+    return Case("subsonic_channel_%dx%d" % (ni, nj), 2, [blk], bcs, [], [prim],
+                Scheme(limiter=limiter), steps, meta={"p0": p0, "rho0": r0, "mach": mach})
+
+
+def farfield_bump(ni=96, nj=48, mach=0.6, alpha_deg=3.0, seed=0, amp=0.05,
+                  limiter=LIMITER_VANLEER, steps=200) -> Case:
+    """2D flow over a bump in a box [0, 3] x [0, 1.5]: farfield at imin, imax
+    and jmax (free stream at Mach ``mach``, angle ``alpha_deg``), slip wall at
+    jmin.  Initial state: the free stream plus smooth seeded perturbations of
+    relative amplitude ``amp``, so that the boundary sees inflow and outflow
+    and both signs of the boundary normal velocity."""
+    nodes = bump_channel_nodes_2d(ni, nj, height=1.5, bump=0.08, jitter=0.02, seed=seed)
+    blk = Block(ni, nj, 1, nodes)
+    a = np.deg2rad(alpha_deg)
+    qinf = np.array([1.0, mach * np.cos(a), mach * np.sin(a), 1.0 / GAMMA])
+    rng = np.random.default_rng(seed + 202)
+    X, Y = cell_centres_index_space(ni, nj)
+    prim = np.stack([qinf[0] * (1.0 + amp * _smooth_field(rng, X, Y)),
+                     qinf[1] + mach * amp * _smooth_field(rng, X, Y),
+                     qinf[2] + mach * amp * _smooth_field(rng, X, Y),
+                     qinf[3] * (1.0 + amp * _smooth_field(rng, X, Y))])
+    bcs = [full_face_patch(2, blk, 0, IMIN, FARFIELD, qinf),
+           full_face_patch(2, blk, 0, IMAX, FARFIELD, qinf),
+           full_face_patch(2, blk, 0, JMIN, SLIP_WALL),
+           full_face_patch(2, blk, 0, JMAX, FARFIELD, qinf)]
+    return Case("farfield_bump_%dx%d_M%g" % (ni, nj, mach), 2, [blk], bcs, [], [prim],
+                Scheme(limiter=limiter), steps, meta={"qinf": qinf})
+
+
+def characteristic_box_3d(dims=(40, 24, 20), seed=0, mach=0.5, amp=0.03,
+                          limiter=LIMITER_VANALBADA, steps=50) -> Case:
+    """3D box on a jittered grid exercising every characteristic boundary:
+    subsonic inflow at imin (direction tilted off the i axis), subsonic
+    outflow at imax, slip wall at jmin, farfield at jmax and kmin,
+    extrapolation at kmax.  Initial state: the free stream plus smooth seeded
+    perturbations."""
+    ni, nj, nk = dims
+    nodes = jittered_periodic_nodes_3d(ni, nj, nk, seed)
+    blk = Block(ni, nj, nk, nodes)
+    d = np.array([1.0, 0.1, 0.05])
+    qinf = np.array([1.0, mach, 0.0, 0.0, 1.0 / GAMMA])
+    p0, r0 = stagnation_state(mach)
+    rng = np.random.default_rng(seed + 303)
+    X, Y, Z = cell_centres_index_space(ni, nj, nk)
+    prim = np.stack([1.0 + amp * _smooth_field(rng, X, Y, Z=Z),
+                     mach * (1.0 + amp * _smooth_field(rng, X, Y, Z=Z)),
+                     mach * amp * _smooth_field(rng, X, Y, Z=Z),
+                     mach * amp * _smooth_field(rng, X, Y, Z=Z),
+                     (1.0 + amp * _smooth_field(rng, X, Y, Z=Z)) / GAMMA])
+    bcs = [full_face_patch(3, blk, 0, IMIN, SUB_INFLOW, [p0, r0, *(d / np.sqrt((d * d).sum()))]),
+           full_face_patch(3, blk, 0, IMAX, SUB_OUTFLOW, [1.0 / GAMMA]),
+           full_face_patch(3, blk, 0, JMIN, SLIP_WALL),
+           full_face_patch(3, blk, 0, JMAX, FARFIELD, qinf),
+           full_face_patch(3, blk, 0, KMIN, FARFIELD, qinf),
+           full_face_patch(3, blk, 0, KMAX, EXTRAP_OUTFLOW)]
+    sch = Scheme(limiter=limiter, lim_eps=[0.0] * 5)
+    return Case("characteristic_box_%dx%dx%d" % (ni, nj, nk), 3, [blk], bcs, [], [prim], sch, steps,
+                meta={"qinf": qinf, "p0": p0, "rho0": r0})
 
 
 def split_block_case(case: Case, splits_i: Sequence[int], splits_j: Sequence[int]) -> Case:
