@@ -64,7 +64,14 @@ enum { CFD_LIM_NONE = 0, CFD_LIM_VANLEER = 1, CFD_LIM_VANALBADA = 2 };
  * F = A (F+(qL) + F-(qR)) with van Leer's Mach-number polynomial split;
  * STEGER_WARMING: the same with F+- = R diag((l +- |l|)/2) R^-1 Q (closed form). */
 enum { CFD_FLUX_ROE = 0, CFD_FLUX_VANLEER_FVS = 1, CFD_FLUX_STEGER_WARMING = 2 };
-enum { CFD_BC_SLIP_WALL = 1, CFD_BC_SUP_INFLOW = 2, CFD_BC_EXTRAP_OUTFLOW = 3 };
+enum {
+  CFD_BC_SLIP_WALL = 1,
+  CFD_BC_SUP_INFLOW = 2,
+  CFD_BC_EXTRAP_OUTFLOW = 3,
+  CFD_BC_FARFIELD = 4,
+  CFD_BC_SUB_INFLOW = 5,
+  CFD_BC_SUB_OUTFLOW = 6
+};
 /* CFL: one global step CFL * min(Omega/lambda) from Q^n each step.  FIXED:
  * dt_fixed.  LOCAL: every cell advances with its own CFL * Omega/lambda from
  * Q^n (steady-state acceleration; time-inaccurate by design).
@@ -110,12 +117,28 @@ cfd_status cfd_destroy(cfd_ctx* ctx);
 cfd_status cfd_add_block(cfd_ctx* ctx, int ni, int nj, int nk, const double* nodes_host, int* block_id);
 
 /* Physical boundary patch on a face range of a block (Sec. 2 boundary types;
- * the paper names the types but prints no formulas; these are the readings):
+ * the paper names the types but prints no formulas; these are the readings).
+ * q_i is the interior cell next to the face, n the unit outward normal.
  *   CFD_BC_SLIP_WALL       mirror ghosts, wall-face flux (0, p_w S, 0), p_w = 1.5 p0 - 0.5 p1
  *   CFD_BC_SUP_INFLOW      both ghost layers = params_host[0..dim+1] (primitive)
- *   CFD_BC_EXTRAP_OUTFLOW  both ghost layers = adjacent interior cell
+ *   CFD_BC_EXTRAP_OUTFLOW  both ghost layers = q_i
+ *   CFD_BC_FARFIELD        params_host = free-stream primitive state (dim+2);
+ *                          both ghost layers = the Riemann-invariant state
+ *                          q_b(q_i, q_inf, n) and the face flux is overwritten
+ *                          with the exact flux F(q_b) . S (Sec. 7.2 V7)
+ *   CFD_BC_SUB_INFLOW      params_host = (p0, rho0, d_1..d_dim): stagnation
+ *                          pressure and density, inflow direction (normalised
+ *                          by the call); p_b = min(p_i, p0), isentropic rho_b
+ *                          and speed, velocity along d
+ *   CFD_BC_SUB_OUTFLOW     params_host = (p_back): q_b = (rho_i, u_i, p_back),
+ *                          q_i where u_i . n >= c_i
+ * Parameters must be finite, densities and pressures positive
+ * (CFD_ERR_NONFINITE), a direction non-zero (CFD_ERR_ARG); params_host is
+ * copied and ignored by the kinds without parameters.
  * Returns a patch id in *patch_id (may be NULL).  Ranges may not overlap other
- * patches or connections (checked at finalize: CFD_ERR_TOPOLOGY). */
+ * patches or connections (checked at finalize: CFD_ERR_TOPOLOGY).  A context
+ * created with the adjoint rejects the last three kinds at finalize
+ * (CFD_ERR_UNSUPPORTED). */
 cfd_status cfd_set_bc(cfd_ctx* ctx, int block, int face, const int lo[2], const int hi[2],
                       int bc_type, const double* params_host, int* patch_id);
 
@@ -143,7 +166,9 @@ cfd_status cfd_bind_workspace(cfd_ctx* ctx, void* dev_ptr, size_t bytes);
  * layout) and recompute the metrics.  Synchronises; CFD_ERR_GRID on a
  * non-positive volume. */
 cfd_status cfd_set_nodes(cfd_ctx* ctx, const double* dev_nodes);
-/* Update the primitive parameters of an inflow patch (host array of dim+2). */
+/* Update the parameters of a patch that has them (supersonic inflow, farfield,
+ * subsonic inflow or outflow; the layout and checks of cfd_set_bc).
+ * CFD_ERR_ARG for a patch kind without parameters.  Synchronises. */
 cfd_status cfd_set_bc_params(cfd_ctx* ctx, int patch_id, const double* params_host);
 
 /* Set the solution from packed conservative (cfd_set_state) or primitive

@@ -7,7 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcfdhip.so")
-SOURCES = ["api.hip", "kernels.hip", "adjoint.hip"]
+OBJ = os.path.join(HERE, "_build")
+SOURCES = ["api.hip", "kernels.hip", "stage2d.hip", "stage3d.hip", "adjoint.hip"]
 ARCH = os.environ.get("CFDHIP_ARCH", "gfx950")
 
 FLAGS = [
@@ -18,7 +19,6 @@ FLAGS = [
     # contract a*b+c into FMA only within one source expression, so the
     # same expression yields the same bits wherever it is inlined
     "-ffp-contract=on",
-    "-shared",
     # keep hipcc from forming packed FP32 instructions (FP64 code, but the
     # setup/reduction paths touch float helpers)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -33,17 +33,40 @@ def hipcc():
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
+def _filtered(proc):
+    return "\n".join(l for l in (proc.stdout + proc.stderr).splitlines() if "packed-fp32-ops" not in l)
+
+
 def build(verbose=False, extra=()):
+    """Compile every source to an object (in parallel: the stage-kernel units
+    dominate) and link the shared library."""
+    os.makedirs(OBJ, exist_ok=True)
+    cc = hipcc()
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
+        cmd = [cc] + FLAGS + list(extra) + ["-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((src, obj, subprocess.Popen(cmd, cwd=HERE, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                                text=True)))
+    errors, objs = [], []
+    for src, obj, p in jobs:
+        out, err = p.communicate()
+        proc = subprocess.CompletedProcess(p.args, p.returncode, out, err)
+        msgs = _filtered(proc)
+        if p.returncode != 0:
+            errors.append("%s:\n%s" % (src, msgs))
+        elif verbose and msgs.strip():
+            print(msgs)
+        objs.append(obj)
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
     out_tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + list(extra) + ["-o", out_tmp] + [os.path.join(CSRC, s) for s in SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out_tmp] + objs
     proc = subprocess.run(cmd, cwd=HERE, capture_output=True, text=True)
-    msgs = "\n".join(l for l in (proc.stdout + proc.stderr).splitlines() if "packed-fp32-ops" not in l)
     if proc.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + msgs)
-    if verbose and msgs.strip():
-        print(msgs)
+        raise RuntimeError("link failed:\n" + _filtered(proc))
     os.replace(out_tmp, LIB)
     return LIB
 

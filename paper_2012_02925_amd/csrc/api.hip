@@ -73,7 +73,8 @@ struct cfd_ctx {
   long long ncells = 0, nnodes = 0, max_cells = 0, max_padded = 0, max_pos = 0, padded_total = 0, max_faces = 0,
             max_nodes = 0;
   long long state_doubles = 0, metric_doubles = 0, xbuf_doubles = 0;
-  int ninflow = 0;
+  bool has_farfield = false;
+  int nparam = 0;  // parameter slots (inflow states, farfield states, stagnation or back pressures)
 
   // workspace
   char* ws = nullptr;
@@ -289,14 +290,43 @@ static cfd_status check_range(cfd_ctx* c, int block, int face, const int lo[2], 
   return CFD_OK;
 }
 
+static bool has_params(int kind) { return kind != CFD_BC_SLIP_WALL && kind != CFD_BC_EXTRAP_OUTFLOW; }
+
+// Checks the parameters of a patch kind and writes their stored form (MAXV
+// doubles, the subsonic-inflow direction normalised) to out.
+static cfd_status check_params(cfd_ctx* c, int kind, const double* params, double* out) {
+  if (!params) return fail(c, CFD_ERR_ARG, "boundary kind %d needs parameters", kind);
+  for (int v = 0; v < MAXV; ++v) out[v] = 0.0;
+  const int nv = c->nvar, dim = c->dim;
+  const int n = kind == CFD_BC_SUB_INFLOW ? 2 + dim : (kind == CFD_BC_SUB_OUTFLOW ? 1 : nv);
+  for (int v = 0; v < n; ++v) {
+    if (!std::isfinite(params[v])) return fail(c, CFD_ERR_NONFINITE, "boundary parameter %d is not finite", v);
+    out[v] = params[v];
+  }
+  if (kind == CFD_BC_SUP_INFLOW || kind == CFD_BC_FARFIELD) {
+    if (!(out[0] > 0.0) || !(out[nv - 1] > 0.0))
+      return fail(c, CFD_ERR_NONFINITE, "boundary density and pressure must be positive");
+  } else if (kind == CFD_BC_SUB_INFLOW) {
+    if (!(out[0] > 0.0) || !(out[1] > 0.0))
+      return fail(c, CFD_ERR_NONFINITE, "stagnation pressure and density must be positive");
+    double s2 = 0.0;
+    for (int d = 0; d < dim; ++d) s2 += out[2 + d] * out[2 + d];
+    if (!(s2 > 0.0)) return fail(c, CFD_ERR_ARG, "subsonic inflow direction is zero");
+    const double len = std::sqrt(s2);
+    for (int d = 0; d < dim; ++d) out[2 + d] /= len;
+  } else if (!(out[0] > 0.0)) {
+    return fail(c, CFD_ERR_NONFINITE, "back pressure must be positive");
+  }
+  return CFD_OK;
+}
+
 extern "C" cfd_status cfd_set_bc(cfd_ctx* c, int block, int face, const int lo[2], const int hi[2], int kind,
                                  const double* params, int* patch_id) {
   if (!c || !lo || !hi) return CFD_ERR_ARG;
   if (c->finalized) return fail(c, CFD_ERR_STATE, "set_bc after finalize");
   cfd_status s = check_range(c, block, face, lo, hi);
   if (s != CFD_OK) return s;
-  if (kind != CFD_BC_SLIP_WALL && kind != CFD_BC_SUP_INFLOW && kind != CFD_BC_EXTRAP_OUTFLOW)
-    return fail(c, CFD_ERR_ARG, "bad boundary kind %d", kind);
+  if (kind < CFD_BC_SLIP_WALL || kind > CFD_BC_SUB_OUTFLOW) return fail(c, CFD_ERR_ARG, "bad boundary kind %d", kind);
   HPatch p{};
   p.block = block;
   p.face = face;
@@ -306,12 +336,9 @@ extern "C" cfd_status cfd_set_bc(cfd_ctx* c, int block, int face, const int lo[2
     p.lo[t] = t < c->dim - 1 ? lo[t] : 0;
     p.hi[t] = t < c->dim - 1 ? hi[t] : 1;
   }
-  if (kind == CFD_BC_SUP_INFLOW) {
-    if (!params) return fail(c, CFD_ERR_ARG, "inflow patch needs parameters");
-    for (int v = 0; v < c->nvar; ++v) p.params[v] = params[v];
-    if (!(p.params[0] > 0.0) || !(p.params[c->nvar - 1] > 0.0))
-      return fail(c, CFD_ERR_NONFINITE, "inflow density and pressure must be positive");
-    p.param_index = c->ninflow++;
+  if (has_params(kind)) {
+    if ((s = check_params(c, kind, params, p.params)) != CFD_OK) return s;
+    p.param_index = c->nparam++;
   }
   c->hpatches.push_back(p);
   if (patch_id) *patch_id = (int)c->hpatches.size() - 1;
@@ -363,6 +390,11 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   if (c->hblocks.empty()) return fail(c, CFD_ERR_STATE, "no blocks");
   if (c->adjoint && c->cfg.flux != CFD_FLUX_ROE)
     return fail(c, CFD_ERR_UNSUPPORTED, "the residual VJP is implemented for the Roe flux");
+  if (c->adjoint)
+    for (auto& p : c->hpatches)
+      if (p.kind > CFD_BC_EXTRAP_OUTFLOW)
+        return fail(c, CFD_ERR_UNSUPPORTED,
+                    "the residual VJP covers slip-wall, supersonic-inflow and extrapolation patches");
   const int dim = c->dim, nv = c->nvar;
   const int nb = (int)c->hblocks.size();
 
@@ -432,6 +464,10 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     B.wall_mask = 0;
     for (auto& p : c->hpatches)
       if (p.block == b && p.kind == CFD_BC_SLIP_WALL) B.wall_mask |= 1 << p.face;
+      else if (p.block == b && p.kind == CFD_BC_FARFIELD) {
+        B.wall_mask |= FARFIELD_MASK_SHIFT << p.face;
+        c->has_farfield = true;
+      }
     c->max_cells = std::max(c->max_cells, ncell);
     const long long pe = (long long)(h.ni + 4) * (h.nj + 4) * (dim == 3 ? h.nk + 4 : 1);
     c->max_padded = std::max(c->max_padded, pe);
@@ -558,7 +594,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->off_metric = take(c->metric_doubles * 8);
   c->off_nodes = take((size_t)c->nnodes * dim * 8);
   c->off_xbuf = take(c->xbuf_doubles * 8);
-  c->off_inflow = take((size_t)std::max(c->ninflow, 1) * MAXV * 8);
+  c->off_inflow = take((size_t)std::max(c->nparam, 1) * MAXV * 8);
   c->off_dt = take(2 * 8);
   c->off_dtmin = take(8);
   c->off_err = take(4);
@@ -647,7 +683,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     c->off_metricbar = take(c->metric_doubles * 8);
     c->off_G = take((size_t)nv * c->ncells * 8);
     c->off_T = take((size_t)nv * c->ncells * 8);
-    c->off_thetabar = take((size_t)std::max(c->ninflow, 1) * MAXV * 8);
+    c->off_thetabar = take((size_t)std::max(c->nparam, 1) * MAXV * 8);
     c->off_part = take(c->part_doubles * 8);
     c->off_partoff = take(c->part_off.size() * sizeof(long long));
     c->off_facemap = take(c->facemap.size() * sizeof(int));
@@ -727,11 +763,11 @@ extern "C" cfd_status cfd_bind_workspace(cfd_ctx* c, void* ptr, size_t bytes) {
       std::memcpy(&nodes[cc * c->nnodes + c->blocks[b].node0], &h.nodes[cc * nn], nn * 8);
   }
   if ((s = upload(c, c->off_nodes, nodes)) != CFD_OK) return s;
-  std::vector<double> inflow((size_t)std::max(c->ninflow, 1) * MAXV, 0.0);
+  std::vector<double> bcp((size_t)std::max(c->nparam, 1) * MAXV, 0.0);
   for (auto& p : c->hpatches)
     if (p.param_index >= 0)
-      for (int v = 0; v < c->nvar; ++v) inflow[(size_t)p.param_index * MAXV + v] = p.params[v];
-  if ((s = upload(c, c->off_inflow, inflow)) != CFD_OK) return s;
+      for (int v = 0; v < MAXV; ++v) bcp[(size_t)p.param_index * MAXV + v] = p.params[v];
+  if ((s = upload(c, c->off_inflow, bcp)) != CFD_OK) return s;
   std::vector<double> dt = {c->cfg.dt_mode == CFD_DT_FIXED ? c->cfg.dt_fixed : 0.0, 0.0};
   if ((s = upload(c, c->off_dt, dt)) != CFD_OK) return s;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -752,12 +788,10 @@ extern "C" cfd_status cfd_set_bc_params(cfd_ctx* c, int patch_id, const double* 
   if (s != CFD_OK) return s;
   if (patch_id < 0 || patch_id >= (int)c->hpatches.size() || !params) return CFD_ERR_ARG;
   HPatch& p = c->hpatches[patch_id];
-  if (p.kind != CFD_BC_SUP_INFLOW) return fail(c, CFD_ERR_ARG, "patch %d is not an inflow patch", patch_id);
-  if (!(params[0] > 0.0) || !(params[c->nvar - 1] > 0.0))
-    return fail(c, CFD_ERR_NONFINITE, "inflow density and pressure must be positive");
-  for (int v = 0; v < c->nvar; ++v) p.params[v] = params[v];
-  double tmp[MAXV] = {0, 0, 0, 0, 0};
-  for (int v = 0; v < c->nvar; ++v) tmp[v] = params[v];
+  if (!has_params(p.kind)) return fail(c, CFD_ERR_ARG, "patch %d has no parameters", patch_id);
+  double tmp[MAXV];
+  if ((s = check_params(c, p.kind, params, tmp)) != CFD_OK) return s;
+  for (int v = 0; v < MAXV; ++v) p.params[v] = tmp[v];
   HIP_TRY(c, hipMemcpyAsync(c->dptr<double>(c->off_inflow) + (size_t)p.param_index * MAXV, tmp, sizeof tmp,
                             hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -785,8 +819,9 @@ static GhostArgs ghost_args(cfd_ctx* c, double* q) {
   g.patches = c->dptr<PatchDev>(c->off_patches);
   g.q = q;
   g.buf = c->dptr<double>(c->off_xbuf);
-  g.inflow = c->dptr<double>(c->off_inflow);
+  g.bcparams = c->dptr<double>(c->off_inflow);
   g.metric = c->metric();
+  g.gas = make_gas(c->cfg.gamma);
   return g;
 }
 
@@ -856,13 +891,13 @@ static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool 
     for (int b = 0; b < nb; ++b) {
       a.tile_begin = c->tile_begin[v][b];
       a.tile_end = c->tile_begin[v][b + 1];
-      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->cfg.limiter, v, a, a.tile_end - a.tile_begin, s));
+      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->cfg.limiter, v, c->has_farfield, a, a.tile_end - a.tile_begin, s));
     }
   } else {
     a.tiles = c->dptr<TileDev>(c->off_tiles_batched[v]);
     a.tile_begin = 0;
     a.tile_end = (int)c->tiles_batched[v].size();
-    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->cfg.limiter, v, a, a.tile_end, s));
+    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->cfg.limiter, v, c->has_farfield, a, a.tile_end, s));
   }
   if (timed) {
     HIP_TRY(c, hipEventRecord(ev->b, s));
@@ -1234,13 +1269,13 @@ static cfd_status vjp_core(cfd_ctx* c, const double* q, const double* Rb, double
 }
 
 static cfd_status copy_thetabar(cfd_ctx* c, double* dev_BCbar) {
-  if (!dev_BCbar || c->ninflow == 0) return CFD_OK;
+  if (!dev_BCbar || c->nparam == 0) return CFD_OK;
   // dJ/dtheta = sum of the per-position partials accumulated since the reset
-  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_thetabar, 0, (size_t)std::max(c->ninflow, 1) * MAXV * 8, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->ws + c->off_thetabar, 0, (size_t)std::max(c->nparam, 1) * MAXV * 8, c->stream));
   VjpArgs a = vjp_args(c, c->stA(), nullptr, 1.0, nullptr, nullptr);
   HIP_TRY(c, launch_vjp_inflow_reduce(c->dim, a, c->stream));
   HIP_TRY(c, hipMemcpy2DAsync(dev_BCbar, c->nvar * 8, c->dptr<double>(c->off_thetabar), MAXV * 8, c->nvar * 8,
-                              c->ninflow, hipMemcpyDeviceToDevice, c->stream));
+                              c->nparam, hipMemcpyDeviceToDevice, c->stream));
   return CFD_OK;
 }
 

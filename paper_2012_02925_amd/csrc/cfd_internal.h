@@ -9,6 +9,7 @@ namespace cfd {
 
 constexpr int NG = 2;    // ghost layers: the four-cell MUSCL stencil of eq. (flux)
 constexpr int MAXV = 5;  // variables in 3D
+constexpr int FARFIELD_MASK_SHIFT = 1 << 8;  // BlockDev::wall_mask: farfield bits above the wall bits
 
 // One structured block in the workspace.  Every padded array of the block
 // (state variables, metric components) shares the same geometry:
@@ -19,7 +20,7 @@ constexpr int MAXV = 5;  // variables in 3D
 struct BlockDev {
   int ni, nj, nk;
   int pi, pj;              // row pitch (doubles), rows per k-plane
-  int wall_mask;           // bit f set: face f carries at least one slip-wall patch
+  int wall_mask;           // bit f: face f carries a slip-wall patch; bit f + 8: a farfield patch
   long long vstride;       // doubles between two padded arrays of this block
   long long origin;        // offset of interior (0,0,0) of array 0 within a state buffer
   long long morigin;       // offset of interior (0,0,0) of metric array 0 within the metric buffer
@@ -56,10 +57,17 @@ struct TransferDev {
   long long buf;                   // offset of the segment in the exchange buffer
 };
 
-enum PatchKind { PK_SLIP_WALL = 1, PK_SUP_INFLOW = 2, PK_EXTRAP_OUTFLOW = 3 };
+enum PatchKind {
+  PK_SLIP_WALL = 1,
+  PK_SUP_INFLOW = 2,
+  PK_EXTRAP_OUTFLOW = 3,
+  PK_FARFIELD = 4,
+  PK_SUB_INFLOW = 5,
+  PK_SUB_OUTFLOW = 6
+};
 
 struct PatchDev {
-  int block, face, kind, param;    // param: index of the inflow state (kind SUP_INFLOW)
+  int block, face, kind, param;    // param: slot of the patch's parameters (MAXV doubles each), or -1
   int lo0, lo1, len0, len1;
 };
 

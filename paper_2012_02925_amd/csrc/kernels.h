@@ -18,8 +18,9 @@ struct GhostArgs {
   int chunk_begin;
   double* q;              // state buffer whose ghosts are filled
   double* buf;            // exchange buffer
-  const double* inflow;   // inflow primitive states, MAXV doubles per inflow patch
+  const double* bcparams;  // boundary parameters, MAXV doubles per parameter slot
   const double* metric;
+  Gas gas;
 };
 
 struct CellArgs {
@@ -50,7 +51,9 @@ struct StageVariant {
 const StageVariant* stage_variants(int dim, int* count);
 hipError_t launch_sumsq(int nvar, const double* R, long long ncells, double* partial, int nparts,
                         double* norms, hipStream_t s);
-hipError_t launch_stage(int dim, int flux, int lim, int variant, const StageArgs& a, int grid, hipStream_t s);
+// ff: some block has a farfield patch (selects the kernels that test for it)
+hipError_t launch_stage(int dim, int flux, int lim, int variant, bool ff, const StageArgs& a, int grid,
+                        hipStream_t s);
 hipError_t launch_ghost(int dim, const GhostArgs& a, int nchunks, hipStream_t s);
 hipError_t launch_set_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
 hipError_t launch_get_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);

@@ -6,7 +6,7 @@
 #include "cfd_internal.h"
 #include "device_math.h"
 #include "kernels.h"
-#include "stage_kernel.h"
+#include "stage_launch.h"
 
 namespace cfd {
 
@@ -25,6 +25,78 @@ __device__ __forceinline__ void mirror_velocity(double* q, const double* S) {
   const double f = 2.0 * un / s2;  // 2 (u . n) n with n = S/|S|
 #pragma unroll
   for (int d = 0; d < DIM; ++d) q[1 + d] -= f * S[d];
+}
+
+// Characteristic boundary states (Sec. 2 names the boundary types; the forms
+// are the textbook ones).  g holds the primitive state of the interior cell
+// next to the face on entry and the boundary state on return; n is the unit
+// normal pointing out of the block.
+//
+// Farfield: Riemann invariants R+ = V_i + 2 c_i/(gamma-1) from the interior
+// and R- = V_inf - 2 c_inf/(gamma-1) from the free stream qf give the normal
+// velocity (R+ + R-)/2 and the sound speed (gamma-1)(R+ - R-)/4; entropy
+// p/rho^gamma and tangential velocity come from the upwind side.  Supersonic
+// inflow takes qf, supersonic outflow keeps the interior state.
+template <int DIM>
+__device__ void farfield_state(double* g, const double* n, const double* qf, const Gas& gs) {
+  constexpr int NV = DIM + 2;
+  double Vi = 0.0, Vf = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    Vi += g[1 + d] * n[d];
+    Vf += qf[1 + d] * n[d];
+  }
+  const double ci = sqrt(gs.gamma * g[NV - 1] / g[0]);
+  const double cf = sqrt(gs.gamma * qf[NV - 1] / qf[0]);
+  if (Vf <= -cf) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) g[v] = qf[v];
+    return;
+  }
+  if (Vi >= ci) return;
+  const double Rp = Vi + 2.0 * ci / gs.gm1;
+  const double Rm = Vf - 2.0 * cf / gs.gm1;
+  const double Vb = 0.5 * (Rp + Rm);
+  const double cb = 0.25 * gs.gm1 * (Rp - Rm);
+  double side[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) side[v] = Vb >= 0.0 ? g[v] : qf[v];
+  const double s = side[NV - 1] / pow(side[0], gs.gamma);
+  const double rb = pow(cb * cb / (gs.gamma * s), 1.0 / gs.gm1);
+  double us = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) us += side[1 + d] * n[d];
+  g[0] = rb;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) g[1 + d] = side[1 + d] - us * n[d] + Vb * n[d];
+  g[NV - 1] = rb * cb * cb / gs.gamma;
+}
+
+// Subsonic inflow with stagnation pressure p0, stagnation density rho0 and
+// unit direction d (P = p0, rho0, d): static pressure from the interior,
+// capped at p0; density and speed from the isentropic relations.
+template <int DIM>
+__device__ void subsonic_inflow_state(double* g, const double* P, const Gas& gs) {
+  constexpr int NV = DIM + 2;
+  const double p0 = P[0], r0 = P[1];
+  const double pb = fmin(g[NV - 1], p0);
+  const double rb = r0 * pow(pb / p0, 1.0 / gs.gamma);
+  const double sp = sqrt(fmax(2.0 * gs.gamma / gs.gm1 * (p0 / r0 - pb / rb), 0.0));
+  g[0] = rb;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) g[1 + d] = sp * P[2 + d];
+  g[NV - 1] = pb;
+}
+
+// Subsonic outflow: the back pressure replaces the interior pressure unless
+// the outflow is supersonic.
+template <int DIM>
+__device__ void subsonic_outflow_state(double* g, const double* n, double pback, const Gas& gs) {
+  constexpr int NV = DIM + 2;
+  double Vi = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) Vi += g[1 + d] * n[d];
+  if (Vi < sqrt(gs.gamma * g[NV - 1] / g[0])) g[NV - 1] = pback;
 }
 
 template <int DIM>
@@ -75,14 +147,16 @@ __global__ void __launch_bounds__(CHUNK) ghost_kernel(GhostArgs a) {
   double g[NV];
   if (p.kind == PK_SUP_INFLOW) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) g[v] = a.inflow[p.param * MAXV + v];
+    for (int v = 0; v < NV; ++v) g[v] = a.bcparams[p.param * MAXV + v];
   } else {
     int si, sj, sk;
     face_cell(B, DIM, p.face, p.kind == PK_SLIP_WALL ? layer : 0, false, t1, t2, si, sj, sk);
     const long long s = pidx(B, si, sj, sk);
 #pragma unroll
     for (int v = 0; v < NV; ++v) g[v] = base[v * vs + s];
-    if (p.kind == PK_SLIP_WALL) {
+    if (p.kind == PK_SUB_INFLOW) {
+      subsonic_inflow_state<DIM>(g, a.bcparams + p.param * MAXV, a.gas);
+    } else if (p.kind != PK_EXTRAP_OUTFLOW) {
       // area vector of the boundary face itself
       int fi, fj, fk;
       face_cell(B, DIM, p.face, 0, (p.face & 1) != 0, t1, t2, fi, fj, fk);
@@ -91,7 +165,20 @@ __global__ void __launch_bounds__(CHUNK) ghost_kernel(GhostArgs a) {
       double S[DIM];
 #pragma unroll
       for (int c = 0; c < DIM; ++c) S[c] = met[ML::S(p.face >> 1, c) * vs + fidx];
-      mirror_velocity<DIM>(g, S);
+      if (p.kind == PK_SLIP_WALL) {
+        mirror_velocity<DIM>(g, S);
+      } else {
+        double s2 = 0.0, n[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) s2 += S[c] * S[c];
+        const double len = sqrt(s2);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) n[c] = (p.face & 1) ? S[c] / len : -(S[c] / len);
+        if (p.kind == PK_FARFIELD)
+          farfield_state<DIM>(g, n, a.bcparams + p.param * MAXV, a.gas);
+        else
+          subsonic_outflow_state<DIM>(g, n, a.bcparams[p.param * MAXV], a.gas);
+      }
     }
   }
   const long long gidx = pidx(B, gi, gj, gk);
@@ -401,31 +488,6 @@ hipError_t launch_sumsq(int nvar, const double* R, long long ncells, double* par
 // ---------------------------------------------------------------------------
 // stage kernel variants
 
-template <int DIM, int LIM, int TX, int TY, int KC, int FLUX>
-static hipError_t launch_stage_t(const StageArgs& a, int grid, hipStream_t s) {
-  if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC, FLUX>), dim3(grid), dim3(TX * TY), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int DIM, int TX, int TY, int KC, int FLUX>
-static hipError_t launch_stage_lim(int lim, const StageArgs& a, int grid, hipStream_t s) {
-  switch (lim) {
-    case LIM_NONE: return launch_stage_t<DIM, LIM_NONE, TX, TY, KC, FLUX>(a, grid, s);
-    case LIM_VANLEER: return launch_stage_t<DIM, LIM_VANLEER, TX, TY, KC, FLUX>(a, grid, s);
-    default: return launch_stage_t<DIM, LIM_VANALBADA, TX, TY, KC, FLUX>(a, grid, s);
-  }
-}
-
-template <int DIM, int TX, int TY, int KC>
-static hipError_t launch_stage_flux(int flux, int lim, const StageArgs& a, int grid, hipStream_t s) {
-  switch (flux) {
-    case FLUX_VANLEER_FVS: return launch_stage_lim<DIM, TX, TY, KC, FLUX_VANLEER_FVS>(lim, a, grid, s);
-    case FLUX_STEGER_WARMING: return launch_stage_lim<DIM, TX, TY, KC, FLUX_STEGER_WARMING>(lim, a, grid, s);
-    default: return launch_stage_lim<DIM, TX, TY, KC, FLUX_ROE>(lim, a, grid, s);
-  }
-}
-
 const StageVariant* stage_variants(int dim, int* count) {
   static const StageVariant v2[] = {{64, 4, 1}, {32, 8, 1}, {16, 16, 1}};
   static const StageVariant v3[] = {{64, 4, 32}, {32, 8, 32}, {32, 8, 64}};
@@ -433,19 +495,9 @@ const StageVariant* stage_variants(int dim, int* count) {
   return dim == 2 ? v2 : v3;
 }
 
-hipError_t launch_stage(int dim, int flux, int lim, int variant, const StageArgs& a, int grid, hipStream_t s) {
-  if (dim == 2) {
-    switch (variant) {
-      case 0: return launch_stage_flux<2, 64, 4, 1>(flux, lim, a, grid, s);
-      case 1: return launch_stage_flux<2, 32, 8, 1>(flux, lim, a, grid, s);
-      default: return launch_stage_flux<2, 16, 16, 1>(flux, lim, a, grid, s);
-    }
-  }
-  switch (variant) {
-    case 0: return launch_stage_flux<3, 64, 4, 32>(flux, lim, a, grid, s);
-    case 1: return launch_stage_flux<3, 32, 8, 32>(flux, lim, a, grid, s);
-    default: return launch_stage_flux<3, 32, 8, 64>(flux, lim, a, grid, s);
-  }
+hipError_t launch_stage(int dim, int flux, int lim, int variant, bool ff, const StageArgs& a, int grid,
+                        hipStream_t s) {
+  return dim == 2 ? launch_stage_2d(flux, lim, variant, ff, a, grid, s) : launch_stage_3d(flux, lim, variant, ff, a, grid, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -10,8 +10,9 @@
 //      a limiter) are computed once per cell into LDS;
 //   3. the face flux (Roe, or a flux-vector splitting) is computed once per
 //      i- and j-face of the tile (faces on the tile edge are shared with the
-//      neighbour tile), the wall override of Sec. 7.2 V7 applied on slip-wall
-//      faces, and stored in LDS;
+//      neighbour tile), the override of Sec. 7.2 V7 applied on slip-wall
+//      faces (wall pressure only) and farfield faces (exact flux of the
+//      boundary state in the ghost cell), and stored in LDS;
 //   4. every cell sums its face fluxes, scales by its inverse volume and either
 //      writes the residual or applies the stage update
 //      Q^(k) = Q^(0) - alpha dt R(Q^(k-1)) (Sec. 2, M-stage Runge-Kutta) and
@@ -61,15 +62,22 @@ struct StageArgs {
 
 __device__ __forceinline__ double wall_pressure(double p0, double p1) { return 1.5 * p0 - 0.5 * p1; }
 
-// true if face `face` of block b at tangential position (t1, t2) is a slip wall
-__device__ __forceinline__ bool is_wall(const StageArgs& a, int b, int face, int t1, int t2) {
+// true if face `face` of block b at tangential position (t1, t2) belongs to a
+// patch of the given kind (slip walls and farfield faces overwrite the flux)
+__device__ __forceinline__ bool patch_at(const StageArgs& a, int kind, int b, int face, int t1, int t2) {
   for (int p = 0; p < a.npatches; ++p) {
     const PatchDev& pt = a.patches[p];
-    if (pt.block == b && pt.face == face && pt.kind == PK_SLIP_WALL && t1 >= pt.lo0 && t1 < pt.lo0 + pt.len0 &&
+    if (pt.block == b && pt.face == face && pt.kind == kind && t1 >= pt.lo0 && t1 < pt.lo0 + pt.len0 &&
         t2 >= pt.lo1 && t2 < pt.lo1 + pt.len1)
       return true;
   }
   return false;
+}
+__device__ __forceinline__ bool is_wall(const StageArgs& a, const BlockDev& B, int b, int face, int t1, int t2) {
+  return face >= 0 && (B.wall_mask & (1 << face)) && patch_at(a, PK_SLIP_WALL, b, face, t1, t2);
+}
+__device__ __forceinline__ bool is_farfield(const StageArgs& a, const BlockDev& B, int b, int face, int t1, int t2) {
+  return face >= 0 && (B.wall_mask & (FARFIELD_MASK_SHIFT << face)) && patch_at(a, PK_FARFIELD, b, face, t1, t2);
 }
 
 // Load through a uniform array base and a per-lane 32-bit byte offset (the
@@ -90,6 +98,17 @@ __device__ __forceinline__ void wall_flux(double pw, const double* S, double* F)
   F[DIM + 1] = 0.0;
 }
 
+// Farfield faces carry the exact flux of the boundary state q_b that the
+// ghost cell holds.  Both face states are set to q_b and the scheme's flux is
+// evaluated on them: every flux here is consistent, F(q, q) = F(q) (the Roe
+// dissipation multiplies state jumps, the split parts sum to the flux), so
+// this is the exact flux up to rounding and shares the flux code.
+template <int NV>
+__device__ __forceinline__ void farfield_states(const double* qb, double* L, double* R) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) L[v] = R[v] = qb[v];
+}
+
 // LDS bytes of one stage-kernel workgroup (must match the arrays below)
 template <int DIM, int LIM, int TX, int TY>
 constexpr int stage_lds_bytes() {
@@ -106,7 +125,9 @@ constexpr int stage_waves() {
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-template <int DIM, int LIM, int TX, int TY, int KC, int FLUX>
+// FF: the launch has farfield faces.  Kernels without them keep the farfield
+// test out of the face loops, whose register budget is tight in 3D.
+template <int DIM, int LIM, int TX, int TY, int KC, int FLUX, bool FF>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, LIM, TX, TY>())))
 stage_kernel(StageArgs a) {
   constexpr int NV = DIM + 2;
@@ -227,9 +248,9 @@ stage_kernel(StageArgs a) {
       }
       if (F) {
         const int kf = k + 1;
-        if (kf == 0 && (B.wall_mask & (1 << 4)) && is_wall(a, tile.block, 4, i, j)) {
+        if (kf == 0 && is_wall(a, B, tile.block, 4, i, j)) {
           wall_flux<3>(wall_pressure(qn[NV - 1], qnn[NV - 1]), Sz, F);
-        } else if (kf == B.nk && (B.wall_mask & (1 << 5)) && is_wall(a, tile.block, 5, i, j)) {
+        } else if (kf == B.nk && is_wall(a, B, tile.block, 5, i, j)) {
           wall_flux<3>(wall_pressure(qcur[NV - 1], pprev), Sz, F);
         } else {
           double L[NV], R[NV];
@@ -241,6 +262,8 @@ stage_kernel(StageArgs a) {
             else
               R[v] = qn[v] - he * snp[v];
           }
+          if (FF && kf == 0 && is_farfield(a, B, tile.block, 4, i, j)) farfield_states<NV>(qcur, L, R);
+          if (FF && kf == B.nk && is_farfield(a, B, tile.block, 5, i, j)) farfield_states<NV>(qn, L, R);
           face_flux<3, FLUX>(L, R, Sz, a.gas, a.efix, a.half_inv_efix, F);
         }
       }
@@ -364,7 +387,7 @@ stage_kernel(StageArgs a) {
       double F[NV];
       if (fx_ok) {
         const int face = i == 0 ? 0 : (i == B.ni ? 1 : -1);
-        if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, j, k)) {
+        if (is_wall(a, B, tile.block, face, j, k)) {
           const double pw = face == 0 ? wall_pressure(sq[NV - 1][own_lp], sq[NV - 1][own_lp + 1])
                                       : wall_pressure(sq[NV - 1][own_lp - 1], sq[NV - 1][own_lp - 2]);
           wall_flux<DIM>(pw, Sx, F);
@@ -375,6 +398,11 @@ stage_kernel(StageArgs a) {
             L[v] = sq[v][own_lp - 1] + he * slx[0][v][ty * SXW + tx];
             R[v] = sq[v][own_lp] - he * slx[NS - 1][v][ty * SXW + tx + 1];
           }
+          if (FF && is_farfield(a, B, tile.block, face, j, k)) {
+            const int gp = face == 0 ? own_lp - 1 : own_lp;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) L[v] = R[v] = sq[v][gp];
+          }
           face_flux<DIM, FLUX>(L, R, Sx, a.gas, a.efix, a.half_inv_efix, F);
         }
 #pragma unroll
@@ -382,7 +410,7 @@ stage_kernel(StageArgs a) {
       }
       if (fy_ok) {
         const int face = j == 0 ? 2 : (j == B.nj ? 3 : -1);
-        if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, i, k)) {
+        if (is_wall(a, B, tile.block, face, i, k)) {
           const double pw = face == 2 ? wall_pressure(sq[NV - 1][own_lp], sq[NV - 1][own_lp + LX])
                                       : wall_pressure(sq[NV - 1][own_lp - LX], sq[NV - 1][own_lp - 2 * LX]);
           wall_flux<DIM>(pw, Sy, F);
@@ -392,6 +420,11 @@ stage_kernel(StageArgs a) {
           for (int v = 0; v < NV; ++v) {
             L[v] = sq[v][own_lp - LX] + he * sly[0][v][ty * TX + tx];
             R[v] = sq[v][own_lp] - he * sly[NS - 1][v][(ty + 1) * TX + tx];
+          }
+          if (FF && is_farfield(a, B, tile.block, face, i, k)) {
+            const int gp = face == 2 ? own_lp - LX : own_lp;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) L[v] = R[v] = sq[v][gp];
           }
           face_flux<DIM, FLUX>(L, R, Sy, a.gas, a.efix, a.half_inv_efix, F);
         }
@@ -432,7 +465,7 @@ stage_kernel(StageArgs a) {
 #pragma unroll
           for (int c = 0; c < DIM; ++c) S[c] = ld_at(met + ML::S(d, c) * vs, fidx);
           const int face = isx ? (fi == B.ni ? 1 : -1) : (fj == B.nj ? 3 : -1);
-          if (face >= 0 && (B.wall_mask & (1 << face)) && is_wall(a, tile.block, face, isx ? fj : fi, k)) {
+          if (is_wall(a, B, tile.block, face, isx ? fj : fi, k)) {
             wall_flux<DIM>(wall_pressure(sq[NV - 1][pL], sq[NV - 1][pL - st]), S, F);
           } else {
             double L[NV], R[NV];
@@ -440,6 +473,10 @@ stage_kernel(StageArgs a) {
             for (int v = 0; v < NV; ++v) {
               L[v] = sq[v][pL] + he * (isx ? slx[0][v][sL] : sly[0][v][sL]);
               R[v] = sq[v][pL + st] - he * (isx ? slx[NS - 1][v][sR] : sly[NS - 1][v][sR]);
+            }
+            if (FF && is_farfield(a, B, tile.block, face, isx ? fj : fi, k)) {
+#pragma unroll
+              for (int v = 0; v < NV; ++v) L[v] = R[v] = sq[v][pL + st];
             }
             face_flux<DIM, FLUX>(L, R, S, a.gas, a.efix, a.half_inv_efix, F);
           }

@@ -146,6 +146,45 @@ def test_block_extent_and_range_errors():
     lib.cfd_destroy(ctx)
 
 
+def test_characteristic_bc_parameter_validation():
+    capi, lib = _lib()
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    K = capi.BC
+    r = (capi.int2([0]), capi.int2([6]))
+    rj = (capi.int2([0]), capi.int2([8]))
+
+    def arr(*v):
+        return ctypes.cast((ctypes.c_double * 5)(*(list(v) + [0.0] * (5 - len(v)))), capi._DP)
+
+    # parameters are required, finite and positive where they are densities or pressures
+    assert lib.cfd_set_bc(ctx, 0, 0, *r, K["farfield"], None, None) == -1
+    assert lib.cfd_set_bc(ctx, 0, 0, *r, K["farfield"], arr(1.0, 0.5, 0.0, -0.7), None) == -6
+    assert lib.cfd_set_bc(ctx, 0, 0, *r, K["farfield"], arr(1.0, float("nan"), 0.0, 0.7), None) == -6
+    assert lib.cfd_set_bc(ctx, 0, 0, *r, K["sub_inflow"], arr(0.0, 1.0, 1.0, 0.0), None) == -6
+    assert lib.cfd_set_bc(ctx, 0, 0, *r, K["sub_inflow"], arr(0.9, 1.1, 0.0, 0.0), None) == -1
+    assert lib.cfd_set_bc(ctx, 0, 1, *r, K["sub_outflow"], arr(-0.7), None) == -6
+    pid = ctypes.c_int()
+    assert lib.cfd_set_bc(ctx, 0, 0, *r, K["sub_inflow"], arr(0.9, 1.1, 2.0, 0.0), ctypes.byref(pid)) == 0
+    assert lib.cfd_set_bc(ctx, 0, 1, *r, K["sub_outflow"], arr(0.7), None) == 0
+    assert lib.cfd_set_bc(ctx, 0, 2, *rj, K["slip_wall"], None, None) == 0
+    assert lib.cfd_set_bc(ctx, 0, 3, *rj, K["farfield"], arr(1.0, 0.5, 0.0, 0.7), None) == 0
+    assert lib.cfd_set_bc(ctx, 0, 3, *rj, 7, None, None) == -1
+    n = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == 0
+    lib.cfd_destroy(ctx)
+    # the residual VJP rejects the characteristic boundaries
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    assert lib.cfd_enable_adjoint(ctx, 1) == 0
+    assert lib.cfd_set_bc(ctx, 0, 0, *r, K["farfield"], arr(1.0, 0.5, 0.0, 0.7), None) == 0
+    assert lib.cfd_set_bc(ctx, 0, 1, *r, K["extrap_outflow"], None, None) == 0
+    assert lib.cfd_connect(ctx, 0, 2, *rj, 0, 3, *rj, 0) == 0
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == -7
+    assert b"residual VJP" in lib.cfd_last_error(ctx)
+    lib.cfd_destroy(ctx)
+
+
 def test_topology_errors():
     capi, lib = _lib()
     ctx = _ctx(capi, lib)
