@@ -21,6 +21,18 @@ also defined when b = 0 (the ratio is never formed):
   van Albada Psi = (r^2 + r)/(1 + r^2)      S(a, b) = ((b^2+e^2) a + (a^2+e^2) b)/(a^2 + b^2 + 2 e^2)
 
 (van Albada with the usual regularisation e, per primitive variable.)
+
+Limiter freezing (Sec. 6, the laminar airfoil case: the limiter is frozen
+late in a steady run so the residual keeps falling instead of oscillating; no
+formula is printed).  Reading: for the symmetric limiters S(a, b) = S(b, a),
+so one value per cell, direction and variable describes the limiter there,
+
+  phi = S(a, b) / ((a + b) / 2)     (0 where a + b = 0, where S = 0 too),
+
+the ratio of the limited slope to the central one, taken from the state at
+the freeze.  Frozen, every product S(a, b) of the kappa-form becomes
+phi (a + b) / 2 with the current differences a, b: the face states are
+then linear in q, and at the freeze state they are unchanged.
 """
 import torch
 
@@ -53,10 +65,26 @@ def psi(r, limiter):
     raise ValueError(limiter)
 
 
-def face_states(q, axis, limiter, eps=1.0, kappa=-1.0, eps2=None):
+def frozen_factor(a, b, limiter, eps2=None):
+    """phi = S(a, b) / ((a + b) / 2), 0 where a + b = 0."""
+    return _safe_div(slope(a, b, limiter, eps2), 0.5 * (a + b))
+
+
+def cell_differences(q, axis):
+    """(Delta_{i-1/2}, Delta_{i+1/2}) of the cells -1 .. n of a padded array
+    (n + 4 cells along ``axis``): the cells that touch the n + 1 faces."""
+    m = q.shape[axis]
+    D = q.narrow(axis, 1, m - 1) - q.narrow(axis, 0, m - 1)
+    return D.narrow(axis, 0, m - 2), D.narrow(axis, 1, m - 2)
+
+
+def face_states(q, axis, limiter, eps=1.0, kappa=-1.0, eps2=None, phi=None):
     """Left/right primitive states on the n+1 faces along ``axis`` of a
     padded array holding n + 4 cells along that axis (two ghost cells on each
-    side).  Face f (0..n) lies between cells f-1 and f."""
+    side).  Face f (0..n) lies between cells f-1 and f.
+
+    ``phi``: frozen limiter factors of the cells -1 .. n (n + 2 along
+    ``axis``), or None for the live limiter."""
     m = q.shape[axis]
     n = m - 4
     D = q.narrow(axis, 1, m - 1) - q.narrow(axis, 0, m - 1)  # D[p] = Delta between padded p, p+1
@@ -64,6 +92,13 @@ def face_states(q, axis, limiter, eps=1.0, kappa=-1.0, eps2=None):
     D0 = D.narrow(axis, 1, n + 1)  # Delta_{i+1/2} = Delta_{f-1/2}
     Dp = D.narrow(axis, 2, n + 1)  # Delta_{i+3/2} = Delta_{f+1/2}
     e2 = eps2
+    if phi is not None:
+        # frozen: S(a, b) -> phi (a + b)/2 of the cell whose differences a, b are
+        sL = phi.narrow(axis, 0, n + 1) * (0.5 * (D0 + Dm))
+        sR = phi.narrow(axis, 1, n + 1) * (0.5 * (Dp + D0))
+        qL = q.narrow(axis, 1, n + 1) + eps / 4.0 * ((1.0 - kappa) * sL + (1.0 + kappa) * sL)
+        qR = q.narrow(axis, 2, n + 1) - eps / 4.0 * ((1.0 + kappa) * sR + (1.0 - kappa) * sR)
+        return qL, qR
     # Psi^+_{i-1/2} Delta_{i-1/2} = S(Delta_{i+1/2}, Delta_{i-1/2});  Psi^-_{i+1/2} Delta_{i+1/2} = S(Delta_{i-1/2}, Delta_{i+1/2})
     qL = q.narrow(axis, 1, n + 1) + eps / 4.0 * ((1.0 - kappa) * slope(D0, Dm, limiter, e2)
                                                  + (1.0 + kappa) * slope(Dm, D0, limiter, e2))

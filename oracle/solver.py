@@ -59,6 +59,7 @@ class Problem:
         self.cfl = sch.cfl
         self.dt_fixed = sch.dt_fixed
         self.local_dt = getattr(sch, "local_dt", False)
+        self.frozen = None  # per block, per direction: frozen limiter factors (muscl.frozen_factor)
         le = sch.lim_eps if sch.lim_eps is not None else [0.0] * self.nvar
         self.lim_eps2 = torch.tensor([e * e for e in le], dtype=F64)
         self.nodes = [torch.tensor(b.nodes, dtype=F64, requires_grad=requires_grad) for b in case.blocks]
@@ -79,11 +80,12 @@ class Problem:
         return [gas.cons_from_prim(torch.tensor(q, dtype=F64), self.gamma) for q in self.case.prims]
 
     # -- residual -----------------------------------------------------------
-    def block_residual_padded(self, qpad, S, vol, walls=()):
+    def block_residual_padded(self, qpad, S, vol, walls=(), phi=None):
         """Residual of one block from a padded primitive array (ghosts given).
 
         ``walls``: boundary patches of the block whose face flux is overwritten
-        (slip walls and farfield faces), or (face, lo, hi) triples of slip walls."""
+        (slip walls and farfield faces), or (face, lo, hi) triples of slip walls.
+        ``phi``: frozen limiter factors of the block per direction, or None."""
         dim = self.dim
         nd = qpad.ndim
         eps2 = self.lim_eps2.reshape([-1] + [1] * (nd - 1))
@@ -96,7 +98,8 @@ class Problem:
                 if a != d:
                     sl[tensor_axis(nd, a)] = slice(2, -2)
             qd = qpad[tuple(sl)]
-            qL, qR = muscl.face_states(qd, ax, self.limiter, self.eps, self.kappa, eps2)
+            qL, qR = muscl.face_states(qd, ax, self.limiter, self.eps, self.kappa, eps2,
+                                       None if phi is None else phi[d])
             F = self.face_flux(qL, qR, S[d])
             for w in walls:
                 face, lo, hi = (w.face, w.lo, w.hi) if isinstance(w, _Patch) else w
@@ -171,8 +174,37 @@ class Problem:
         q_list = [gas.prim_from_cons(Q, self.gamma) for Q in Q_list]
         S_list = [m[0] for m in met]
         pads = fill_ghosts(self, q_list, S_list)
-        return [self.block_residual_padded(pads[b], met[b][0], met[b][1], self.walls_of(b))
+        return [self.block_residual_padded(pads[b], met[b][0], met[b][1], self.walls_of(b),
+                                           None if self.frozen is None else self.frozen[b])
                 for b in range(len(Q_list))]
+
+    # -- limiter freezing ---------------------------------------------------
+    def freeze_limiter(self, Q_list, met=None):
+        """Freeze the limiter at the state Q_list (muscl.frozen_factor of every
+        cell -1 .. n per direction, from the ghost-filled primitives); later
+        residuals use the frozen factors until unfreeze_limiter()."""
+        if self.limiter == "none":
+            raise ValueError("no limiter to freeze")
+        met = self.metrics() if met is None else met
+        q_list = [gas.prim_from_cons(Q, self.gamma) for Q in Q_list]
+        pads = fill_ghosts(self, q_list, [m[0] for m in met])
+        dim = self.dim
+        self.frozen = []
+        for qpad in pads:
+            nd = qpad.ndim
+            eps2 = self.lim_eps2.reshape([-1] + [1] * (nd - 1))
+            per_dir = []
+            for d in range(dim):
+                sl = [slice(None)] * nd
+                for a in range(dim):
+                    if a != d:
+                        sl[tensor_axis(nd, a)] = slice(2, -2)
+                Dm, Dp = muscl.cell_differences(qpad[tuple(sl)], tensor_axis(nd, d))
+                per_dir.append(muscl.frozen_factor(Dp, Dm, self.limiter, eps2))
+            self.frozen.append(per_dir)
+
+    def unfreeze_limiter(self):
+        self.frozen = None
 
     # -- time step ----------------------------------------------------------
     def cell_dt(self, Q, S, vol):
