@@ -193,6 +193,25 @@ cfd_status cfd_residual(cfd_ctx* ctx, double* dev_R);
  * partition of the cells and fixed reduction order. */
 cfd_status cfd_residual_norms(cfd_ctx* ctx, double* dev_R, double* dev_norms);
 
+/* Limiter freezing for steady runs (Sec. 6: the limiter is frozen late in a
+ * steady run so the residual keeps falling; no formula is printed).  Reading:
+ * per cell, direction and primitive variable the factor
+ *   phi = S(a, b) / ((a + b)/2)   (0 where a + b = 0),
+ * S the limiter's slope form and a, b the cell's forward and backward
+ * differences, is taken from the current state; while frozen every limited
+ * slope is phi (a + b)/2 with the current differences.  The residual is
+ * unchanged at the freeze state.
+ * cfd_enable_limiter_freezing reserves dim * (dim+2) padded arrays per block
+ * in the workspace; call it before cfd_finalize (CFD_ERR_STATE after;
+ * CFD_ERR_ARG without a limiter; an adjoint context rejects it at finalize
+ * with CFD_ERR_UNSUPPORTED).  cfd_freeze_limiter(ctx, 1) computes the factors
+ * from the current state (asynchronous on the stream) and switches every
+ * later residual and step to them; cfd_freeze_limiter(ctx, 0) returns to the
+ * live limiter.  CFD_ERR_STATE if freezing was not enabled or no state is
+ * set. */
+cfd_status cfd_enable_limiter_freezing(cfd_ctx* ctx, int enable);
+cfd_status cfd_freeze_limiter(cfd_ctx* ctx, int freeze);
+
 /* Global CFL time step CFL * min(Omega / lambda) of the current state, or the
  * fixed step, written to dev_dt[0]; with CFD_DT_LOCAL the smallest cell step. */
 cfd_status cfd_time_step(cfd_ctx* ctx, double* dev_dt);

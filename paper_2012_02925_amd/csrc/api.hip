@@ -109,6 +109,10 @@ struct cfd_ctx {
   static constexpr int SUM_PARTS = 1024;
   static constexpr int NORM_PARTS = 1024;
   size_t off_dtloc = 0, off_normpart = 0;
+  bool freezing = false;  // workspace holds frozen-limiter arrays (cfd_enable_limiter_freezing)
+  bool frozen = false;    // stage kernels use the frozen factors
+  long long phi_doubles = 0;
+  size_t off_phi = 0;
 
   // timing
   bool profiling = false;
@@ -390,6 +394,8 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   if (c->hblocks.empty()) return fail(c, CFD_ERR_STATE, "no blocks");
   if (c->adjoint && c->cfg.flux != CFD_FLUX_ROE)
     return fail(c, CFD_ERR_UNSUPPORTED, "the residual VJP is implemented for the Roe flux");
+  if (c->adjoint && c->freezing)
+    return fail(c, CFD_ERR_UNSUPPORTED, "the residual VJP differentiates the live limiter; freezing is not supported");
   if (c->adjoint)
     for (auto& p : c->hpatches)
       if (p.kind > CFD_BC_EXTRAP_OUTFLOW)
@@ -426,7 +432,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
 
   // --- block layout ---------------------------------------------------------
   c->blocks.resize(nb);
-  long long cursor = 0, mcursor = 0, fcursor = 0, packed = 0, node0 = 0;
+  long long cursor = 0, mcursor = 0, fcursor = 0, lcursor = 0, packed = 0, node0 = 0;
   const int nmet = dim * dim + 1;
   const int nfb = (2 * nv + 3) * dim;
   c->max_cells = c->max_padded = c->max_pos = 0;
@@ -455,6 +461,11 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     mcursor = align_ll(mcursor + 14 + (nmet - 1) * B.vstride + padded, 16);
     B.forigin = fcursor + 14 + K;
     fcursor = align_ll(fcursor + 14 + (nfb - 1) * B.vstride + padded, 16);
+    B.lorigin = 0;
+    if (c->freezing) {
+      B.lorigin = lcursor + 14 + K;
+      lcursor = align_ll(lcursor + 14 + (dim * nv - 1) * B.vstride + padded, 16);
+    }
     B.packed = packed;
     const long long ncell = (long long)h.ni * h.nj * h.nk;
     packed += ncell;
@@ -488,6 +499,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->state_doubles = cursor;
   c->metric_doubles = mcursor;
   c->facebar_doubles = fcursor;
+  c->phi_doubles = lcursor;
 
   // --- transfers, patches and ghost-fill chunks ------------------------------
   c->xfers.clear();
@@ -600,6 +612,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->off_err = take(4);
   c->off_normpart = take((size_t)cfd_ctx::NORM_PARTS * MAXV * 8);
   if (c->cfg.dt_mode == CFD_DT_LOCAL) c->off_dtloc = take((size_t)c->ncells * 8);
+  if (c->freezing) c->off_phi = take((size_t)c->phi_doubles * 8);
   c->off_blocks = take(c->blocks.size() * sizeof(BlockDev));
   c->off_xfers = take(c->xfers.size() * sizeof(TransferDev));
   c->off_patches = take(c->patches.size() * sizeof(PatchDev));
@@ -840,6 +853,7 @@ static StageArgs stage_args(cfd_ctx* c) {
   for (int v = 0; v < MAXV; ++v) a.e2[v] = c->cfg.lim_eps[v] * c->cfg.lim_eps[v];
   a.dtloc = c->cfg.dt_mode == CFD_DT_LOCAL ? c->dptr<double>(c->off_dtloc) : nullptr;
   a.cfl = c->cfg.cfl;
+  a.phi = c->frozen ? c->dptr<double>(c->off_phi) : nullptr;
   return a;
 }
 
@@ -891,13 +905,13 @@ static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool 
     for (int b = 0; b < nb; ++b) {
       a.tile_begin = c->tile_begin[v][b];
       a.tile_end = c->tile_begin[v][b + 1];
-      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->cfg.limiter, v, c->has_farfield, a, a.tile_end - a.tile_begin, s));
+      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->frozen ? LIM_FROZEN : c->cfg.limiter, v, c->has_farfield, a, a.tile_end - a.tile_begin, s));
     }
   } else {
     a.tiles = c->dptr<TileDev>(c->off_tiles_batched[v]);
     a.tile_begin = 0;
     a.tile_end = (int)c->tiles_batched[v].size();
-    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->cfg.limiter, v, c->has_farfield, a, a.tile_end, s));
+    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->frozen ? LIM_FROZEN : c->cfg.limiter, v, c->has_farfield, a, a.tile_end, s));
   }
   if (timed) {
     HIP_TRY(c, hipEventRecord(ev->b, s));
@@ -1195,6 +1209,35 @@ extern "C" cfd_status cfd_query(cfd_ctx* c, int what, long long* value) {
 
 // ---------------------------------------------------------------------------
 // adjoint
+
+extern "C" cfd_status cfd_enable_limiter_freezing(cfd_ctx* c, int enable) {
+  if (!c) return CFD_ERR_ARG;
+  if (c->finalized) return fail(c, CFD_ERR_STATE, "enable_limiter_freezing after finalize");
+  if (enable && c->cfg.limiter == CFD_LIM_NONE) return fail(c, CFD_ERR_ARG, "no limiter to freeze");
+  c->freezing = enable != 0;
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_freeze_limiter(cfd_ctx* c, int freeze) {
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  if (!c->freezing)
+    return fail(c, CFD_ERR_STATE, "limiter freezing not enabled before finalize (cfd_enable_limiter_freezing)");
+  if (freeze) {
+    if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
+    if ((s = fill_ghosts(c, c->stA(), c->stream)) != CFD_OK) return s;
+    FreezeArgs a{};
+    a.blocks = c->dptr<BlockDev>(c->off_blocks);
+    a.q = c->stA();
+    a.phi = c->dptr<double>(c->off_phi);
+    a.limiter = c->cfg.limiter;
+    for (int v = 0; v < MAXV; ++v) a.e2[v] = c->cfg.lim_eps[v] * c->cfg.lim_eps[v];
+    HIP_TRY(c, launch_freeze(c->dim, a, c->max_padded, (int)c->blocks.size(), c->stream));
+  }
+  if (c->frozen != (freeze != 0)) release_graph(c);  // the captured step names the stage kernels
+  c->frozen = freeze != 0;
+  return CFD_OK;
+}
 
 extern "C" cfd_status cfd_enable_adjoint(cfd_ctx* c, int enable) {
   if (!c) return CFD_ERR_ARG;

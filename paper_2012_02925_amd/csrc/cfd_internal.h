@@ -25,6 +25,7 @@ struct BlockDev {
   long long origin;        // offset of interior (0,0,0) of array 0 within a state buffer
   long long morigin;       // offset of interior (0,0,0) of metric array 0 within the metric buffer
   long long forigin;       // offset of interior (0,0,0) of face-scratch array 0 (adjoint)
+  long long lorigin;       // offset of interior (0,0,0) of frozen-limiter array 0 (d * nvar + v)
   long long packed;        // first cell of the block in the packed [var][cell] layout
   long long node0;         // first node of the block in the concatenated node layout
   long long ncell_total;   // cells of all blocks (stride between packed variables)

@@ -54,7 +54,7 @@ __device__ __forceinline__ double rsq2(double x) {
 // every kappa of eq. (flux).  A denominator below 1e-250 returns 0: the
 // differences are then below 1e-250 (van Leer) or 1e-125 (van Albada without
 // regularisation) and so is the exact slope.
-enum { LIM_NONE = 0, LIM_VANLEER = 1, LIM_VANALBADA = 2 };
+enum { LIM_NONE = 0, LIM_VANLEER = 1, LIM_VANALBADA = 2, LIM_FROZEN = 3 };
 constexpr double SLOPE_TINY = 1e-250;
 
 template <int LIM>
@@ -89,6 +89,23 @@ __device__ __forceinline__ void cell_slopes(double dm, double dp, double e2, dou
     sm = sp;
   }
 }
+
+// Limiter freezing: the frozen factor phi = S(a, b) / ((a + b)/2) of a cell
+// (a, b its forward and backward differences at the freeze), in closed form:
+// van Leer 4ab/(a + b)^2 for ab > 0, else 0; van Albada
+// 2(ab + e^2)/(a^2 + b^2 + 2e^2), 0 where a + b = 0 (S vanishes there).
+// Frozen, the slope is phi (a + b)/2 with the current differences.
+template <int LIM>
+__device__ __forceinline__ double frozen_factor(double a, double b, double e2) {
+  if constexpr (LIM == LIM_VANLEER) {
+    const double ab = a * b, s = a + b;
+    return ab > 0.0 ? 4.0 * ab / (s * s) : 0.0;
+  } else {
+    if (a + b == 0.0) return 0.0;
+    return 2.0 * (a * b + e2) / (a * a + b * b + 2.0 * e2);
+  }
+}
+__device__ __forceinline__ double frozen_slope(double phi, double dm, double dp) { return phi * (0.5 * (dm + dp)); }
 
 template <int DIM>
 __device__ __forceinline__ void prim_to_cons(const double* q, const Gas& g, double* Q) {

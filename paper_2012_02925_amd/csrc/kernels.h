@@ -58,6 +58,17 @@ hipError_t launch_ghost(int dim, const GhostArgs& a, int nchunks, hipStream_t s)
 hipError_t launch_set_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
 hipError_t launch_get_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
 hipError_t launch_cell_dt(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
+
+// Limiter freezing: frozen factors of every cell -1 .. n per direction from a
+// ghost-filled primitive state (0 elsewhere in the padded arrays).
+struct FreezeArgs {
+  const BlockDev* blocks;
+  const double* q;  // primitive state buffer, ghosts filled
+  double* phi;      // frozen-limiter buffer: per block dim * nvar padded arrays
+  int limiter;      // LIM_VANLEER or LIM_VANALBADA
+  double e2[MAXV];
+};
+hipError_t launch_freeze(int dim, const FreezeArgs& a, long long max_padded, int nblocks, hipStream_t s);
 hipError_t launch_export_padded(int dim, const CellArgs& a, long long max_padded, int nblocks, hipStream_t s);
 hipError_t launch_metrics(int dim, const MetricArgs& a, long long max_pos, int nblocks, hipStream_t s);
 hipError_t launch_dt_promote(double* dt, unsigned long long* dtmin, double cfl, int promote, double* out,

@@ -540,6 +540,56 @@ hipError_t launch_cell_dt(int dim, const CellArgs& a, long long max_cells, int n
   return hipGetLastError();
 }
 
+// One thread per padded cell of a block (grid.y = block).  A cell gets the
+// factor of direction d if it touches a face along d (index -1 .. n along d)
+// and is interior along the other directions; every other entry is 0.
+template <int DIM>
+__global__ void freeze_kernel(FreezeArgs a) {
+  constexpr int NV = DIM + 2;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const int ei = B.ni + 4, ej = B.nj + 4, ek = DIM == 3 ? B.nk + 4 : 1;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long long)ei * ej * ek) return;
+  const int i = (int)(c % ei) - 2;
+  const long long r = c / ei;
+  const int j = (int)(r % ej) - 2;
+  const int k = DIM == 3 ? (int)(r / ej) - 2 : 0;
+  const long long vs = B.vstride;
+  const long long p = pidx(B, i, j, k);
+  const double* q = a.q + B.origin;
+  double* phi = a.phi + B.lorigin;
+  const int idx[3] = {i, j, k};
+  const int ext[3] = {B.ni, B.nj, B.nk};
+  const long long step[3] = {1, B.pi, (long long)B.pi * B.pj};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    bool ok = idx[d] >= -1 && idx[d] <= ext[d];
+#pragma unroll
+    for (int e = 0; e < DIM; ++e)
+      if (e != d) ok = ok && idx[e] >= 0 && idx[e] < ext[e];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double f = 0.0;
+      if (ok) {
+        const double q0 = q[v * vs + p];
+        const double dm = q0 - q[v * vs + p - step[d]];
+        const double dp = q[v * vs + p + step[d]] - q0;
+        f = a.limiter == LIM_VANLEER ? frozen_factor<LIM_VANLEER>(dp, dm, 0.0)
+                                     : frozen_factor<LIM_VANALBADA>(dp, dm, a.e2[v]);
+      }
+      phi[(d * NV + v) * vs + p] = f;
+    }
+  }
+}
+
+hipError_t launch_freeze(int dim, const FreezeArgs& a, long long max_padded, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(freeze_kernel<2>, cell_grid(max_padded, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(freeze_kernel<3>, cell_grid(max_padded, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_export_padded(int dim, const CellArgs& a, long long max_padded, int nblocks, hipStream_t s) {
   if (dim == 2)
     hipLaunchKernelGGL(export_padded_kernel<2>, cell_grid(max_padded, nblocks), dim3(256), 0, s, a);

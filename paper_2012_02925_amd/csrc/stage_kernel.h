@@ -58,6 +58,7 @@ struct StageArgs {
   double efix;
   double half_inv_efix;  // 0.5 / efix (0 when efix = 0)
   double e2[MAXV];       // van Albada regularisation squared
+  const double* phi;     // frozen limiter factors (LIM_FROZEN): padded arrays d * nvar + v
 };
 
 __device__ __forceinline__ double wall_pressure(double p0, double p1) { return 1.5 * p0 - 0.5 * p1; }
@@ -186,6 +187,7 @@ stage_kernel(StageArgs a) {
     const long long K = (DIM == 3 ? 2LL * B.pj + 2 : 2LL) * B.pi + 2;
     const double* qin = a.qin + (B.origin - K);
     const double* met = a.metric + (B.morigin - K);
+    const double* phib = LIM == LIM_FROZEN ? a.phi + (B.lorigin - K) : nullptr;
     const unsigned p8 = (unsigned)plane * 8u;
     const int kbeg = DIM == 3 ? tile.k0 : 0;
     const int kend = DIM == 3 ? min(tile.k0 + KC, B.nk) : 1;
@@ -242,7 +244,10 @@ stage_kernel(StageArgs a) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         double sp, sm;
-        cell_slopes<LIM>(qn[v] - qcur[v], qnn[v] - qn[v], e2[v], kap, sp, sm);
+        if constexpr (LIM == LIM_FROZEN)
+          sp = frozen_slope(ld_at(phib + (2 * NV + v) * vs, zoff(k + 1)), qn[v] - qcur[v], qnn[v] - qn[v]);
+        else
+          cell_slopes<LIM>(qn[v] - qcur[v], qnn[v] - qn[v], e2[v], kap, sp, sm);
         snp[v] = sp;
         if constexpr (NS == 2) snm[v] = sm;
       }
@@ -337,6 +342,16 @@ stage_kernel(StageArgs a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double sp, sm;
+          if constexpr (LIM == LIM_FROZEN) {
+            // cells beyond the padded block compute slopes nobody reads
+            const double fx = own_in_pad ? ld_at(phib + v * vs, ok) : 0.0;
+            const double fy = own_in_pad ? ld_at(phib + (NV + v) * vs, ok) : 0.0;
+            slx[0][v][ty * SXW + tx + 1] =
+                frozen_slope(fx, sq[v][own_lp] - sq[v][own_lp - 1], sq[v][own_lp + 1] - sq[v][own_lp]);
+            sly[0][v][(ty + 1) * TX + tx] =
+                frozen_slope(fy, sq[v][own_lp] - sq[v][own_lp - LX], sq[v][own_lp + LX] - sq[v][own_lp]);
+            continue;
+          }
           cell_slopes<LIM>(sq[v][own_lp] - sq[v][own_lp - 1], sq[v][own_lp + 1] - sq[v][own_lp], e2[v], kap, sp,
                            sm);
           slx[0][v][ty * SXW + tx + 1] = sp;
@@ -348,7 +363,7 @@ stage_kernel(StageArgs a) {
         }
       }
       if (tid < NXS) {
-        int p, st, dst;
+        int p, st, dst, hi, hj;  // LDS cell, stride, slope slot, block cell
         bool isx;
         if (tid < 2 * TY) {  // i-slopes of cells i0-1 and i0+TX
           const int r = tid >> 1, side = tid & 1;
@@ -357,6 +372,8 @@ stage_kernel(StageArgs a) {
           st = 1;
           dst = r * SXW + c;
           isx = true;
+          hi = i0 - 1 + c;
+          hj = j0 + r;
         } else {  // j-slopes of rows j0-1 and j0+TY
           const int e = tid - 2 * TY;
           const int c = e % TX, side = e / TX;
@@ -365,11 +382,20 @@ stage_kernel(StageArgs a) {
           st = LX;
           dst = r * TX + c;
           isx = false;
+          hi = i0 + c;
+          hj = j0 - 1 + r;
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           double sp, sm;
-          cell_slopes<LIM>(sq[v][p] - sq[v][p - st], sq[v][p + st] - sq[v][p], e2[v], kap, sp, sm);
+          if constexpr (LIM == LIM_FROZEN) {
+            const bool in_pad = hi <= B.ni + 1 && hj <= B.nj + 1;
+            const double f =
+                in_pad ? ld_at(phib + ((isx ? 0 : NV) + v) * vs, (unsigned)((pidx(B, hi, hj, k) + K) * 8)) : 0.0;
+            sp = frozen_slope(f, sq[v][p] - sq[v][p - st], sq[v][p + st] - sq[v][p]);
+          } else {
+            cell_slopes<LIM>(sq[v][p] - sq[v][p - st], sq[v][p + st] - sq[v][p], e2[v], kap, sp, sm);
+          }
           if (isx) {
             slx[0][v][dst] = sp;
             if constexpr (NS == 2) slx[NS - 1][v][dst] = sm;

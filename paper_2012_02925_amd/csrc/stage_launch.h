@@ -25,6 +25,7 @@ inline hipError_t launch_stage_lim(int lim, bool ff, const StageArgs& a, int gri
   switch (lim) {
     case LIM_NONE: return launch_stage_t<DIM, LIM_NONE, TX, TY, KC, FLUX>(ff, a, grid, s);
     case LIM_VANLEER: return launch_stage_t<DIM, LIM_VANLEER, TX, TY, KC, FLUX>(ff, a, grid, s);
+    case LIM_FROZEN: return launch_stage_t<DIM, LIM_FROZEN, TX, TY, KC, FLUX>(ff, a, grid, s);
     default: return launch_stage_t<DIM, LIM_VANALBADA, TX, TY, KC, FLUX>(ff, a, grid, s);
   }
 }
@@ -40,5 +41,7 @@ inline hipError_t launch_stage_flux(int flux, int lim, bool ff, const StageArgs&
 
 hipError_t launch_stage_2d(int flux, int lim, int variant, bool ff, const StageArgs& a, int grid, hipStream_t s);
 hipError_t launch_stage_3d(int flux, int lim, int variant, bool ff, const StageArgs& a, int grid, hipStream_t s);
+hipError_t launch_stage_3d_fvs(int flux, int lim, int variant, bool ff, const StageArgs& a, int grid,
+                               hipStream_t s);
 
 }  // namespace cfd

@@ -63,10 +63,12 @@ class Solver:
 
     # -- construction ------------------------------------------------------
     @classmethod
-    def from_case(cls, case, device="cuda", state=True, adjoint=False):
+    def from_case(cls, case, device="cuda", state=True, adjoint=False, freezing=False):
         s = cls(case.dim, case.scheme, device)
         if adjoint:
             s.enable_adjoint()
+        if freezing:
+            s.enable_limiter_freezing()
         for b in case.blocks:
             s.add_block(b.ni, b.nj, b.nk, b.nodes)
         for p in case.bcs:
@@ -150,6 +152,14 @@ class Solver:
         N = torch.empty(self.nvar, dtype=F64, device=self.device)
         self._check(self.lib.cfd_residual_norms(self.ctx, dptr(R), dptr(N)))
         return R, N
+
+    def enable_limiter_freezing(self, enable=True):
+        """Reserve the frozen-limiter arrays (before finalize)."""
+        self._check(self.lib.cfd_enable_limiter_freezing(self.ctx, 1 if enable else 0))
+
+    def freeze_limiter(self, freeze=True):
+        """Freeze the limiter at the current state (True) or return to the live limiter."""
+        self._check(self.lib.cfd_freeze_limiter(self.ctx, 1 if freeze else 0))
 
     def time_step(self):
         dt = torch.empty(1, dtype=F64, device=self.device)

@@ -185,6 +185,38 @@ def test_characteristic_bc_parameter_validation():
     lib.cfd_destroy(ctx)
 
 
+def test_limiter_freezing_validation():
+    capi, lib = _lib()
+    ctx = _ctx(capi, lib, limiter=0)
+    assert lib.cfd_enable_limiter_freezing(ctx, 1) == -1  # nothing to freeze
+    lib.cfd_destroy(ctx)
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    _periodic(capi, lib, ctx, 0, 8, 6)
+    n0 = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n0)) == 0
+    assert lib.cfd_enable_limiter_freezing(ctx, 1) == -2  # after finalize
+    assert lib.cfd_freeze_limiter(ctx, 1) == -2           # no workspace, not enabled
+    lib.cfd_destroy(ctx)
+    # the frozen factors take dim * nvar padded arrays of workspace
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    _periodic(capi, lib, ctx, 0, 8, 6)
+    assert lib.cfd_enable_limiter_freezing(ctx, 1) == 0
+    n1 = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n1)) == 0
+    assert n1.value >= n0.value + 2 * 4 * (8 + 4) * (6 + 4) * 8
+    lib.cfd_destroy(ctx)
+    # not with the adjoint
+    ctx = _ctx(capi, lib)
+    _add(capi, lib, ctx, 8, 6)
+    _periodic(capi, lib, ctx, 0, 8, 6)
+    assert lib.cfd_enable_limiter_freezing(ctx, 1) == 0
+    assert lib.cfd_enable_adjoint(ctx, 1) == 0
+    assert lib.cfd_finalize(ctx, ctypes.byref(n1)) == -7
+    lib.cfd_destroy(ctx)
+
+
 def test_topology_errors():
     capi, lib = _lib()
     ctx = _ctx(capi, lib)
