@@ -16,7 +16,9 @@ Readings (the paper names the boundary types but prints no formulas):
   * supersonic inflow: both ghost layers hold the inflow primitive state;
   * extrapolated outflow: both ghost layers copy the adjacent interior cell;
   * farfield, subsonic inflow, subsonic outflow: both ghost layers hold the
-    characteristic boundary state of oracle/bc.py.
+    characteristic boundary state of oracle/bc.py;
+  * adiabatic no-slip wall: ghost layer g copies interior layer g with the
+    velocity negated (rho and p copied, so T too).
 Corner ghosts are not filled; the dimension-by-dimension stencil never reads them.
 
 Arrays: interior primitive state ``q`` (nvar, [nk,] nj, ni); padded state
@@ -144,6 +146,9 @@ def fill_ghosts(problem, q_list, S_list):
             if p.kind == "slip_wall":
                 Sf = face_area_slab(S_list[p.block][p.face // 2], dim, p.face, p.lo, p.hi)
                 vals = mirror(interior_layer(q, dim, p.face, g - 1, p.lo, p.hi), Sf)
+            elif p.kind == "noslip_wall":
+                lay = interior_layer(q, dim, p.face, g - 1, p.lo, p.hi)
+                vals = torch.cat([lay[:1], -lay[1:-1], lay[-1:]])
             elif p.kind == "extrap_outflow":
                 vals = interior_layer(q, dim, p.face, 0, p.lo, p.hi)
             elif p.kind == "sup_inflow":

@@ -20,12 +20,16 @@
 * Runge-Kutta: Sec. 2, the explicit M-step scheme of Jameson, Schmidt and
   Turkel: Q^(k) = Q^(0) - alpha_k dt R(Q^(k-1)), alpha_k = 1/(M - k + 1).
 * Objective: J = sum over slip-wall faces of p_w |S| (integrated wall pressure).
+* Laminar Navier-Stokes (viscosity > 0): R = R_inviscid - Rv with the
+  viscous residual of oracle/viscous.py; no-slip walls take the inviscid wall
+  override too; the time step adds the viscous rate of oracle/viscous.py to
+  lambda.
 """
 from __future__ import annotations
 
 import torch
 
-from . import fvs, gas, metrics as metrics_mod, muscl, roe
+from . import fvs, gas, metrics as metrics_mod, muscl, roe, viscous
 from .ghosts import boundary_state, face_area_slab, fill_ghosts, interior_layer, tangential_axes, tensor_axis
 
 F64 = torch.float64
@@ -60,6 +64,8 @@ class Problem:
         self.dt_fixed = sch.dt_fixed
         self.local_dt = getattr(sch, "local_dt", False)
         self.frozen = None  # per block, per direction: frozen limiter factors (muscl.frozen_factor)
+        self.mu = float(getattr(sch, "viscosity", 0.0))
+        self.prandtl = float(getattr(sch, "prandtl", 0.72))
         le = sch.lim_eps if sch.lim_eps is not None else [0.0] * self.nvar
         self.lim_eps2 = torch.tensor([e * e for e in le], dtype=F64)
         self.nodes = [torch.tensor(b.nodes, dtype=F64, requires_grad=requires_grad) for b in case.blocks]
@@ -167,16 +173,20 @@ class Problem:
 
     def walls_of(self, b):
         """Patches of block b whose face flux is overwritten: slip walls and farfield."""
-        return [p for p in self.bcs if p.block == b and p.kind in ("slip_wall", "farfield")]
+        return [p for p in self.bcs if p.block == b and p.kind in ("slip_wall", "noslip_wall", "farfield")]
 
     def residual(self, Q_list, met=None):
         met = self.metrics() if met is None else met
         q_list = [gas.prim_from_cons(Q, self.gamma) for Q in Q_list]
         S_list = [m[0] for m in met]
         pads = fill_ghosts(self, q_list, S_list)
-        return [self.block_residual_padded(pads[b], met[b][0], met[b][1], self.walls_of(b),
-                                           None if self.frozen is None else self.frozen[b])
-                for b in range(len(Q_list))]
+        R = [self.block_residual_padded(pads[b], met[b][0], met[b][1], self.walls_of(b),
+                                        None if self.frozen is None else self.frozen[b])
+             for b in range(len(Q_list))]
+        if self.mu > 0.0:
+            Rv = viscous.viscous_residual(self, pads, self.nodes, met)
+            R = [r - rv for r, rv in zip(R, Rv)]
+        return R
 
     # -- limiter freezing ---------------------------------------------------
     def freeze_limiter(self, Q_list, met=None):
@@ -219,6 +229,8 @@ class Problem:
             axS = tensor_axis(Sd.ndim, d)
             Sbar = 0.5 * (Sd.narrow(axS, 0, n) + Sd.narrow(axS, 1, n))
             lam = lam + (vel * Sbar).sum(0).abs() + c * torch.sqrt((Sbar * Sbar).sum(0))
+        if self.mu > 0.0:
+            lam = lam + viscous.viscous_rate(q, S, vol, self.mu, self.gamma, self.prandtl)
         return vol / lam
 
     def time_step(self, Q_list, met=None):

@@ -41,6 +41,7 @@ EXTRAP_OUTFLOW = "extrap_outflow"
 FARFIELD = "farfield"  # params: free-stream primitive state
 SUB_INFLOW = "sub_inflow"  # params: (p0, rho0, direction)
 SUB_OUTFLOW = "sub_outflow"  # params: (p_back,)
+NOSLIP_WALL = "noslip_wall"  # adiabatic no-slip wall
 
 LIMITER_NONE = "none"
 LIMITER_VANLEER = "vanleer"
@@ -98,6 +99,8 @@ class Scheme:
     cfl: float = 0.5
     dt_fixed: Optional[float] = None  # None = global CFL time step recomputed every step
     local_dt: bool = False  # local time stepping: every cell with its own CFL step (steady runs)
+    viscosity: float = 0.0  # laminar Navier-Stokes when > 0: mu = M_inf / Re in free-stream units
+    prandtl: float = 0.72
 
 
 @dataclasses.dataclass
