@@ -70,7 +70,8 @@ enum {
   CFD_BC_EXTRAP_OUTFLOW = 3,
   CFD_BC_FARFIELD = 4,
   CFD_BC_SUB_INFLOW = 5,
-  CFD_BC_SUB_OUTFLOW = 6
+  CFD_BC_SUB_OUTFLOW = 6,
+  CFD_BC_NOSLIP_WALL = 7
 };
 /* CFL: one global step CFL * min(Omega/lambda) from Q^n each step.  FIXED:
  * dt_fixed.  LOCAL: every cell advances with its own CFL * Omega/lambda from
@@ -97,6 +98,9 @@ typedef struct {
   int flux;             /* CFD_FLUX_*: inviscid face flux (Sec. 2 lists Roe's flux-difference
                            splitting and van Leer's and Steger-Warming's flux-vector
                            splittings); the residual VJP needs CFD_FLUX_ROE */
+  double viscosity;     /* laminar Navier-Stokes when > 0: constant viscosity in these units
+                           (rho_inf = c_inf = 1), mu = M_inf / Re per unit length; 0 = Euler */
+  double prandtl;       /* Prandtl number (0.72) when viscosity > 0 */
 } cfd_config;
 
 /* Version string of the library build. */
@@ -132,12 +136,15 @@ cfd_status cfd_add_block(cfd_ctx* ctx, int ni, int nj, int nk, const double* nod
  *                          and speed, velocity along d
  *   CFD_BC_SUB_OUTFLOW     params_host = (p_back): q_b = (rho_i, u_i, p_back),
  *                          q_i where u_i . n >= c_i
+ *   CFD_BC_NOSLIP_WALL     adiabatic no-slip wall: ghost layer g copies interior
+ *                          layer g with the velocity negated; the inviscid face
+ *                          flux is the wall flux of CFD_BC_SLIP_WALL
  * Parameters must be finite, densities and pressures positive
  * (CFD_ERR_NONFINITE), a direction non-zero (CFD_ERR_ARG); params_host is
  * copied and ignored by the kinds without parameters.
  * Returns a patch id in *patch_id (may be NULL).  Ranges may not overlap other
  * patches or connections (checked at finalize: CFD_ERR_TOPOLOGY).  A context
- * created with the adjoint rejects the last three kinds at finalize
+ * created with the adjoint rejects the last four kinds at finalize
  * (CFD_ERR_UNSUPPORTED). */
 cfd_status cfd_set_bc(cfd_ctx* ctx, int block, int face, const int lo[2], const int hi[2],
                       int bc_type, const double* params_host, int* patch_id);
@@ -183,7 +190,14 @@ cfd_status cfd_get_state(cfd_ctx* ctx, double* dev_Q);
 /* Residual R(Q) of the current state, packed conservative layout, with
  * dQ/dt = -R: ghost fill (connections, then physical patches), MUSCL face
  * states, the configured face flux on every face, wall-flux override, flux
- * divergence / volume. */
+ * divergence / volume.  With viscosity > 0 (laminar Navier-Stokes, Sec. 2,
+ * eq. (governing)) R also subtracts the viscous part Rv = (1/Omega) sum
+ * F_v . S_out: Stokes stresses tau = mu (grad u + grad u^T - 2/3 div u I),
+ * Theta = u . tau + k grad T with T = gamma p / rho and k = mu / ((gamma-1) Pr);
+ * face gradients by Green's theorem over each face's dual volume (the two cell
+ * centres and the face's pseudo-nodes, which average the interior and
+ * face-ghost cells around a grid node); the CFL steps then add
+ * 4 max(4/3, gamma/Pr) (mu/rho) sum_d |Sbar_d|^2 / Omega to lambda. */
 cfd_status cfd_residual(cfd_ctx* ctx, double* dev_R);
 
 /* cfd_residual into dev_R, plus dev_norms[v] = sqrt(sum over all cells of

@@ -13,6 +13,7 @@
 
 #include "../../include/cfdhip.h"
 #include "adjoint.h"
+#include "viscous.h"
 #include "cfd_internal.h"
 #include "kernels.h"
 #include "stage_kernel.h"
@@ -109,6 +110,9 @@ struct cfd_ctx {
   static constexpr int SUM_PARTS = 1024;
   static constexpr int NORM_PARTS = 1024;
   size_t off_dtloc = 0, off_normpart = 0;
+  bool viscous = false;   // laminar Navier-Stokes (cfg.viscosity > 0)
+  long long center_doubles = 0;
+  size_t off_centers = 0, off_npos = 0, off_nval = 0, off_rv = 0;
   bool freezing = false;  // workspace holds frozen-limiter arrays (cfd_enable_limiter_freezing)
   bool frozen = false;    // stage kernels use the frozen factors
   long long phi_doubles = 0;
@@ -234,8 +238,11 @@ extern "C" cfd_status cfd_create(const cfd_config* cfg, void* stream, cfd_ctx** 
   if (!(cfg->efix >= 0.0) || !(cfg->muscl_eps >= 0.0)) return CFD_ERR_ARG;
   for (int v = 0; v < MAXV; ++v)
     if (!(cfg->lim_eps[v] >= 0.0)) return CFD_ERR_ARG;
+  if (!(cfg->viscosity >= 0.0) || !std::isfinite(cfg->viscosity)) return CFD_ERR_ARG;
+  if (cfg->viscosity > 0.0 && !(cfg->prandtl > 0.0)) return CFD_ERR_ARG;
   cfd_ctx* c = new cfd_ctx();
   c->cfg = *cfg;
+  c->viscous = cfg->viscosity > 0.0;
   c->dim = cfg->dim;
   c->nvar = cfg->dim + 2;
   c->stream = reinterpret_cast<hipStream_t>(stream);
@@ -294,7 +301,9 @@ static cfd_status check_range(cfd_ctx* c, int block, int face, const int lo[2], 
   return CFD_OK;
 }
 
-static bool has_params(int kind) { return kind != CFD_BC_SLIP_WALL && kind != CFD_BC_EXTRAP_OUTFLOW; }
+static bool has_params(int kind) {
+  return kind != CFD_BC_SLIP_WALL && kind != CFD_BC_EXTRAP_OUTFLOW && kind != CFD_BC_NOSLIP_WALL;
+}
 
 // Checks the parameters of a patch kind and writes their stored form (MAXV
 // doubles, the subsonic-inflow direction normalised) to out.
@@ -330,7 +339,7 @@ extern "C" cfd_status cfd_set_bc(cfd_ctx* c, int block, int face, const int lo[2
   if (c->finalized) return fail(c, CFD_ERR_STATE, "set_bc after finalize");
   cfd_status s = check_range(c, block, face, lo, hi);
   if (s != CFD_OK) return s;
-  if (kind < CFD_BC_SLIP_WALL || kind > CFD_BC_SUB_OUTFLOW) return fail(c, CFD_ERR_ARG, "bad boundary kind %d", kind);
+  if (kind < CFD_BC_SLIP_WALL || kind > CFD_BC_NOSLIP_WALL) return fail(c, CFD_ERR_ARG, "bad boundary kind %d", kind);
   HPatch p{};
   p.block = block;
   p.face = face;
@@ -394,6 +403,8 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   if (c->hblocks.empty()) return fail(c, CFD_ERR_STATE, "no blocks");
   if (c->adjoint && c->cfg.flux != CFD_FLUX_ROE)
     return fail(c, CFD_ERR_UNSUPPORTED, "the residual VJP is implemented for the Roe flux");
+  if (c->adjoint && c->viscous)
+    return fail(c, CFD_ERR_UNSUPPORTED, "the residual VJP is implemented for the Euler equations");
   if (c->adjoint && c->freezing)
     return fail(c, CFD_ERR_UNSUPPORTED, "the residual VJP differentiates the live limiter; freezing is not supported");
   if (c->adjoint)
@@ -432,7 +443,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
 
   // --- block layout ---------------------------------------------------------
   c->blocks.resize(nb);
-  long long cursor = 0, mcursor = 0, fcursor = 0, lcursor = 0, packed = 0, node0 = 0;
+  long long cursor = 0, mcursor = 0, fcursor = 0, lcursor = 0, ccursor = 0, packed = 0, node0 = 0;
   const int nmet = dim * dim + 1;
   const int nfb = (2 * nv + 3) * dim;
   c->max_cells = c->max_padded = c->max_pos = 0;
@@ -461,6 +472,11 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     mcursor = align_ll(mcursor + 14 + (nmet - 1) * B.vstride + padded, 16);
     B.forigin = fcursor + 14 + K;
     fcursor = align_ll(fcursor + 14 + (nfb - 1) * B.vstride + padded, 16);
+    B.corigin = 0;
+    if (c->viscous) {
+      B.corigin = ccursor + 14 + K;
+      ccursor = align_ll(ccursor + 14 + (dim - 1) * B.vstride + padded, 16);
+    }
     B.lorigin = 0;
     if (c->freezing) {
       B.lorigin = lcursor + 14 + K;
@@ -474,7 +490,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     node0 += nnode;
     B.wall_mask = 0;
     for (auto& p : c->hpatches)
-      if (p.block == b && p.kind == CFD_BC_SLIP_WALL) B.wall_mask |= 1 << p.face;
+      if (p.block == b && (p.kind == CFD_BC_SLIP_WALL || p.kind == CFD_BC_NOSLIP_WALL)) B.wall_mask |= 1 << p.face;
       else if (p.block == b && p.kind == CFD_BC_FARFIELD) {
         B.wall_mask |= FARFIELD_MASK_SHIFT << p.face;
         c->has_farfield = true;
@@ -500,6 +516,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->metric_doubles = mcursor;
   c->facebar_doubles = fcursor;
   c->phi_doubles = lcursor;
+  c->center_doubles = ccursor;
 
   // --- transfers, patches and ghost-fill chunks ------------------------------
   c->xfers.clear();
@@ -613,6 +630,12 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->off_normpart = take((size_t)cfd_ctx::NORM_PARTS * MAXV * 8);
   if (c->cfg.dt_mode == CFD_DT_LOCAL) c->off_dtloc = take((size_t)c->ncells * 8);
   if (c->freezing) c->off_phi = take((size_t)c->phi_doubles * 8);
+  if (c->viscous) {
+    c->off_centers = take((size_t)c->center_doubles * 8);
+    c->off_npos = take((size_t)c->nnodes * dim * 8);
+    c->off_nval = take((size_t)c->nnodes * (dim + 1) * 8);
+    c->off_rv = take((size_t)c->ncells * (dim + 1) * 8);
+  }
   c->off_blocks = take(c->blocks.size() * sizeof(BlockDev));
   c->off_xfers = take(c->xfers.size() * sizeof(TransferDev));
   c->off_patches = take(c->patches.size() * sizeof(PatchDev));
@@ -716,6 +739,30 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
 
 // ---------------------------------------------------------------------------
 
+static ViscArgs visc_args(cfd_ctx* c, const double* q) {
+  ViscArgs v{};
+  v.blocks = c->dptr<BlockDev>(c->off_blocks);
+  v.xfers = c->dptr<TransferDev>(c->off_xfers);
+  v.patches = c->dptr<PatchDev>(c->off_patches);
+  v.chunks = c->dptr<ChunkDev>(c->off_chunks1);
+  v.nodes = c->dptr<double>(c->off_nodes);
+  v.metric = c->metric();
+  v.centers = c->dptr<double>(c->off_centers);
+  v.npos = c->dptr<double>(c->off_npos);
+  v.nval = c->dptr<double>(c->off_nval);
+  v.q = q;
+  v.rv = c->dptr<double>(c->off_rv);
+  v.mu = c->cfg.viscosity;
+  v.kcond = c->cfg.viscosity > 0.0 ? c->cfg.viscosity / ((c->cfg.gamma - 1.0) * c->cfg.prandtl) : 0.0;
+  v.gamma = c->cfg.gamma;
+  return v;
+}
+
+static double visc_cv(const cfd_ctx* c) {
+  if (!c->viscous) return 0.0;
+  return 4.0 * std::max(4.0 / 3.0, c->cfg.gamma / c->cfg.prandtl) * c->cfg.viscosity;
+}
+
 static cfd_status recompute_metrics(cfd_ctx* c) {
   HIP_TRY(c, hipMemsetAsync(c->dptr<int>(c->off_err), 0, sizeof(int), c->stream));
   MetricArgs m{c->dptr<BlockDev>(c->off_blocks), c->dptr<double>(c->off_nodes), c->metric(), c->dptr<int>(c->off_err)};
@@ -725,6 +772,15 @@ static cfd_status recompute_metrics(cfd_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (err) return fail(c, CFD_ERR_GRID, "grid has a non-positive or non-finite cell volume");
   c->dt_valid = false;
+  if (c->viscous) {
+    // cell centres, their first ghost layer (all interior centres first), pseudo-node positions
+    ViscArgs v = visc_args(c, nullptr);
+    const int nb = (int)c->blocks.size();
+    HIP_TRY(c, launch_cell_centers(c->dim, v, c->max_cells, nb, c->stream));
+    HIP_TRY(c, launch_ghost_centers(c->dim, v, (int)c->chunks1.size(), c->stream));
+    HIP_TRY(c, launch_pseudo_nodes(c->dim, v, 0, c->max_nodes, nb, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   return CFD_OK;
 }
 
@@ -822,6 +878,7 @@ static CellArgs cell_args(cfd_ctx* c) {
   a.dtmin = c->dptr<unsigned long long>(c->off_dtmin);
   a.err = c->dptr<int>(c->off_err);
   a.gas = make_gas(c->cfg.gamma);
+  a.visc_cv = visc_cv(c);
   return a;
 }
 
@@ -854,7 +911,23 @@ static StageArgs stage_args(cfd_ctx* c) {
   a.dtloc = c->cfg.dt_mode == CFD_DT_LOCAL ? c->dptr<double>(c->off_dtloc) : nullptr;
   a.cfl = c->cfg.cfl;
   a.phi = c->frozen ? c->dptr<double>(c->off_phi) : nullptr;
+  a.rv = c->viscous ? c->dptr<double>(c->off_rv) : nullptr;
+  a.visc_cv = visc_cv(c);
   return a;
+}
+
+static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s);
+
+// Ghost fill of state buffer q and, for the Navier-Stokes equations, the
+// viscous residual of q that the next stage-kernel launch subtracts.
+static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s) {
+  cfd_status st = fill_ghosts(c, q, s);
+  if (st != CFD_OK || !c->viscous) return st;
+  ViscArgs v = visc_args(c, q);
+  const int nb = (int)c->blocks.size();
+  HIP_TRY(c, launch_pseudo_nodes(c->dim, v, 1, c->max_nodes, nb, s));
+  HIP_TRY(c, launch_viscous(c->dim, v, c->max_cells, nb, s));
+  return CFD_OK;
 }
 
 // Fill every ghost layer of state buffer q: pack + physical patches, then unpack.
@@ -933,7 +1006,7 @@ static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
   double* in = A;
   for (int k = 1; k <= M; ++k) {
     double* out = (k == M) ? A : ((k % 2) ? Bf : Cf);
-    cfd_status st = fill_ghosts(c, in, s);
+    cfd_status st = stage_prep(c, in, s);
     if (st != CFD_OK) return st;
     StageArgs a = stage_args(c);
     a.qin = in;
@@ -1021,7 +1094,7 @@ extern "C" cfd_status cfd_residual(cfd_ctx* c, double* dev_R) {
   if (s != CFD_OK) return s;
   if (!dev_R) return CFD_ERR_ARG;
   if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
-  s = fill_ghosts(c, c->stA(), c->stream);
+  s = stage_prep(c, c->stA(), c->stream);
   if (s != CFD_OK) return s;
   StageArgs a = stage_args(c);
   a.qin = c->stA();
@@ -1119,7 +1192,7 @@ extern "C" cfd_status cfd_autotune(cfd_ctx* c, int reps, int* chosen) {
   if (s != CFD_OK) return s;
   if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
   if (reps < 1) reps = 1;
-  s = fill_ghosts(c, c->stA(), c->stream);
+  s = stage_prep(c, c->stA(), c->stream);
   if (s != CFD_OK) return s;
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));

@@ -26,6 +26,7 @@ struct BlockDev {
   long long morigin;       // offset of interior (0,0,0) of metric array 0 within the metric buffer
   long long forigin;       // offset of interior (0,0,0) of face-scratch array 0 (adjoint)
   long long lorigin;       // offset of interior (0,0,0) of frozen-limiter array 0 (d * nvar + v)
+  long long corigin;       // offset of interior (0,0,0) of cell-centre array 0 (viscous)
   long long packed;        // first cell of the block in the packed [var][cell] layout
   long long node0;         // first node of the block in the concatenated node layout
   long long ncell_total;   // cells of all blocks (stride between packed variables)
@@ -64,7 +65,8 @@ enum PatchKind {
   PK_EXTRAP_OUTFLOW = 3,
   PK_FARFIELD = 4,
   PK_SUB_INFLOW = 5,
-  PK_SUB_OUTFLOW = 6
+  PK_SUB_OUTFLOW = 6,
+  PK_NOSLIP_WALL = 7
 };
 
 struct PatchDev {

@@ -35,6 +35,7 @@ struct CellArgs {
   int* err;
   int flag_primitive;
   Gas gas;
+  double visc_cv;  // viscous time-step coefficient (0: inviscid)
 };
 
 struct MetricArgs {

@@ -150,11 +150,16 @@ __global__ void __launch_bounds__(CHUNK) ghost_kernel(GhostArgs a) {
     for (int v = 0; v < NV; ++v) g[v] = a.bcparams[p.param * MAXV + v];
   } else {
     int si, sj, sk;
-    face_cell(B, DIM, p.face, p.kind == PK_SLIP_WALL ? layer : 0, false, t1, t2, si, sj, sk);
+    const bool mirror = p.kind == PK_SLIP_WALL || p.kind == PK_NOSLIP_WALL;
+    face_cell(B, DIM, p.face, mirror ? layer : 0, false, t1, t2, si, sj, sk);
     const long long s = pidx(B, si, sj, sk);
 #pragma unroll
     for (int v = 0; v < NV; ++v) g[v] = base[v * vs + s];
-    if (p.kind == PK_SUB_INFLOW) {
+    if (p.kind == PK_NOSLIP_WALL) {
+      // adiabatic no-slip wall: velocity negated, rho and p (so T) copied
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) g[1 + d] = -g[1 + d];
+    } else if (p.kind == PK_SUB_INFLOW) {
       subsonic_inflow_state<DIM>(g, a.bcparams + p.param * MAXV, a.gas);
     } else if (p.kind != PK_EXTRAP_OUTFLOW) {
       // area vector of the boundary face itself
@@ -265,7 +270,7 @@ __global__ void __launch_bounds__(256) cell_dt_kernel(CellArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) w[v] = q[v * vs];
     const double cs = sqrt(a.gas.gamma * w[NV - 1] / w[0]);
-    double lam = 0.0;
+    double lam = 0.0, s2sum = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       const long long step = d == 0 ? 1 : (d == 1 ? (long long)B.pi : (long long)B.pi * B.pj);
@@ -277,7 +282,9 @@ __global__ void __launch_bounds__(256) cell_dt_kernel(CellArgs a) {
         s2 += sb * sb;
       }
       lam += fabs(un) + cs * sqrt(s2);
+      s2sum += s2;
     }
+    if (a.visc_cv > 0.0) lam += a.visc_cv / w[0] * s2sum * met[ML::INVVOL * vs];
     m = 1.0 / (lam * met[ML::INVVOL * vs]);
     if (a.dtloc) a.dtloc[B.packed + c] = a.cfl * m;
   }

@@ -59,26 +59,30 @@ struct StageArgs {
   double half_inv_efix;  // 0.5 / efix (0 when efix = 0)
   double e2[MAXV];       // van Albada regularisation squared
   const double* phi;     // frozen limiter factors (LIM_FROZEN): padded arrays d * nvar + v
+  const double* rv;      // viscous residual (momentum.., energy), packed, subtracted from R; or null
+  double visc_cv;        // viscous time-step coefficient 4 max(4/3, gamma/Pr) mu (0: inviscid)
 };
 
 __device__ __forceinline__ double wall_pressure(double p0, double p1) { return 1.5 * p0 - 0.5 * p1; }
 
 // true if face `face` of block b at tangential position (t1, t2) belongs to a
-// patch of the given kind (slip walls and farfield faces overwrite the flux)
-__device__ __forceinline__ bool patch_at(const StageArgs& a, int kind, int b, int face, int t1, int t2) {
+// patch whose kind is in the bit set `kinds` (walls and farfield faces
+// overwrite the flux)
+__device__ __forceinline__ bool patch_at(const StageArgs& a, int kinds, int b, int face, int t1, int t2) {
   for (int p = 0; p < a.npatches; ++p) {
     const PatchDev& pt = a.patches[p];
-    if (pt.block == b && pt.face == face && pt.kind == kind && t1 >= pt.lo0 && t1 < pt.lo0 + pt.len0 &&
+    if (pt.block == b && pt.face == face && ((kinds >> pt.kind) & 1) && t1 >= pt.lo0 && t1 < pt.lo0 + pt.len0 &&
         t2 >= pt.lo1 && t2 < pt.lo1 + pt.len1)
       return true;
   }
   return false;
 }
 __device__ __forceinline__ bool is_wall(const StageArgs& a, const BlockDev& B, int b, int face, int t1, int t2) {
-  return face >= 0 && (B.wall_mask & (1 << face)) && patch_at(a, PK_SLIP_WALL, b, face, t1, t2);
+  return face >= 0 && (B.wall_mask & (1 << face)) &&
+         patch_at(a, (1 << PK_SLIP_WALL) | (1 << PK_NOSLIP_WALL), b, face, t1, t2);
 }
 __device__ __forceinline__ bool is_farfield(const StageArgs& a, const BlockDev& B, int b, int face, int t1, int t2) {
-  return face >= 0 && (B.wall_mask & (FARFIELD_MASK_SHIFT << face)) && patch_at(a, PK_FARFIELD, b, face, t1, t2);
+  return face >= 0 && (B.wall_mask & (FARFIELD_MASK_SHIFT << face)) && patch_at(a, 1 << PK_FARFIELD, b, face, t1, t2);
 }
 
 // Load through a uniform array base and a per-lane 32-bit byte offset (the
@@ -560,6 +564,10 @@ stage_kernel(StageArgs a) {
           if constexpr (DIM == 3) div += fzd[v];
           R[v] = div * iv;
         }
+        if (a.rv) {
+#pragma unroll
+          for (int v = 1; v < NV; ++v) R[v] -= a.rv[(v - 1) * B.ncell_total + pcell];
+        }
         if (!update) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) a.Rout[v * B.ncell_total + pcell] = R[v];
@@ -579,7 +587,7 @@ stage_kernel(StageArgs a) {
           if (a.dtmin) {
             // Omega / lambda with lambda = sum_d |u . Sbar_d| + c |Sbar_d|
             const double c = sqrt(a.gas.gamma * qnew[NV - 1] / qnew[0]);
-            double lam = 0.0;
+            double lam = 0.0, s2sum = 0.0;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
               const unsigned step = d == 0 ? 8u : (d == 1 ? 8u * B.pi : p8);
@@ -592,7 +600,9 @@ stage_kernel(StageArgs a) {
                 s2 += sb * sb;
               }
               lam += fabs(un) + c * sqrt(s2);
+              s2sum += s2;
             }
+            if (a.visc_cv > 0.0) lam += a.visc_cv / qnew[0] * s2sum * iv;
             const double om = 1.0 / (lam * iv);
             my_min = fmin(my_min, om);
             if (a.dtloc) a.dtloc[pcell] = a.cfl * om;

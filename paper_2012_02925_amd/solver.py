@@ -27,6 +27,8 @@ def config_from_scheme(dim, scheme):
     cfg.efix = scheme.efix
     cfg.rk_stages = scheme.rk_stages
     cfg.flux = capi.FLUX[getattr(scheme, "flux", "roe")]
+    cfg.viscosity = float(getattr(scheme, "viscosity", 0.0))
+    cfg.prandtl = float(getattr(scheme, "prandtl", 0.72))
     if scheme.dt_fixed is not None:
         cfg.dt_mode = capi.DT_FIXED
         cfg.dt_fixed = float(scheme.dt_fixed)

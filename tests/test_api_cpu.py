@@ -169,7 +169,7 @@ def test_characteristic_bc_parameter_validation():
     assert lib.cfd_set_bc(ctx, 0, 1, *r, K["sub_outflow"], arr(0.7), None) == 0
     assert lib.cfd_set_bc(ctx, 0, 2, *rj, K["slip_wall"], None, None) == 0
     assert lib.cfd_set_bc(ctx, 0, 3, *rj, K["farfield"], arr(1.0, 0.5, 0.0, 0.7), None) == 0
-    assert lib.cfd_set_bc(ctx, 0, 3, *rj, 7, None, None) == -1
+    assert lib.cfd_set_bc(ctx, 0, 3, *rj, 8, None, None) == -1
     n = ctypes.c_size_t()
     assert lib.cfd_finalize(ctx, ctypes.byref(n)) == 0
     lib.cfd_destroy(ctx)
@@ -214,6 +214,34 @@ def test_limiter_freezing_validation():
     assert lib.cfd_enable_limiter_freezing(ctx, 1) == 0
     assert lib.cfd_enable_adjoint(ctx, 1) == 0
     assert lib.cfd_finalize(ctx, ctypes.byref(n1)) == -7
+    lib.cfd_destroy(ctx)
+
+
+def test_navier_stokes_config_validation():
+    capi, lib = _lib()
+    ctx = ctypes.c_void_p()
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, viscosity=-1e-3)), None, ctypes.byref(ctx)) == -1
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, viscosity=1e-3, prandtl=0.0)), None, ctypes.byref(ctx)) == -1
+    # the viscous workspace: centres, pseudo-nodes, viscous residual
+    n0, n1 = ctypes.c_size_t(), ctypes.c_size_t()
+    for visc, n in ((0.0, n0), (1e-3, n1)):
+        ctx = _ctx(capi, lib, viscosity=visc, prandtl=0.72)
+        _add(capi, lib, ctx, 8, 6)
+        _periodic(capi, lib, ctx, 0, 8, 6)
+        assert lib.cfd_finalize(ctx, ctypes.byref(n)) == 0
+        lib.cfd_destroy(ctx)
+    assert n1.value >= n0.value + 8 * (9 * 7 * (2 + 3) + 48 * 3)
+    # no-slip walls take no parameters; the adjoint rejects viscosity
+    ctx = _ctx(capi, lib, viscosity=1e-3, prandtl=0.72)
+    _add(capi, lib, ctx, 8, 6)
+    r = (capi.int2([0]), capi.int2([8]))
+    assert lib.cfd_set_bc(ctx, 0, 2, *r, capi.BC["noslip_wall"], None, None) == 0
+    assert lib.cfd_set_bc(ctx, 0, 3, *r, capi.BC["noslip_wall"], None, None) == 0
+    assert lib.cfd_connect(ctx, 0, 0, capi.int2([0]), capi.int2([6]), 0, 1, capi.int2([0]), capi.int2([6]), 0) == 0
+    assert lib.cfd_enable_adjoint(ctx, 1) == 0
+    n = ctypes.c_size_t()
+    assert lib.cfd_finalize(ctx, ctypes.byref(n)) == -7
+    assert b"Euler" in lib.cfd_last_error(ctx)
     lib.cfd_destroy(ctx)
 
 

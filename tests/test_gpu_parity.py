@@ -390,3 +390,55 @@ def test_limiter_freezing_modes_bitwise():
         s.rk_step(4)
         outs.append(s.get_state().cpu())
     assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+# laminar Navier-Stokes: viscous residual (Green's-theorem face gradients),
+# no-slip walls, viscous time-step term
+def _viscous(case, mu, noslip=False):
+    case.scheme.viscosity = mu
+    if noslip:
+        for p in case.bcs:
+            if p.kind == synth.SLIP_WALL:
+                p.kind = synth.NOSLIP_WALL
+    case.name += "_ns"
+    return case
+
+
+NS_CASES = {
+    "square_periodic_48x40": lambda: _viscous(synth.jittered_periodic_square(48, 40, seed=3), 0.01),
+    "channel_noslip_96x40": lambda: _viscous(synth.subsonic_channel(96, 40, mach=0.5, seed=5), 2e-3, noslip=True),
+    "ramp_noslip_100x70": lambda: _viscous(synth.compression_ramp(100, 70), 1e-3, noslip=True),
+    "patchwork_3x3": lambda: _viscous(synth.patchwork(seed=2, nbx=3, nby=3, side_lo=8, side_hi=40, h=1.0 / 64), 5e-3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(NS_CASES))
+def test_navier_stokes_residual_and_steps(name):
+    import oracle
+    _say("case: NS", name)
+    case = NS_CASES[name]()
+    s = check_residual(case)
+    P = oracle.Problem(case)
+    dt0 = s.time_step().item()
+    ref = float(P.time_step(P.initial_state()))
+    assert abs(dt0 - ref) <= 1e-13 * ref, (dt0, ref)
+    s.set_variant(1)
+    Qref, dts = oracle_run(case, 15)
+    s.rk_step(15)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    _say("  after 15 steps", rep)
+    assert ok, rep
+
+
+@pytest.mark.parametrize("which", ["periodic_box", "char_box_noslip"])
+def test_navier_stokes_3d(which):
+    _say("case: NS 3D", which)
+    if which == "periodic_box":
+        case = _viscous(synth.jittered_periodic_box(dims=(40, 36, 34), seed=9), 0.01)
+    else:
+        case = _viscous(synth.characteristic_box_3d((40, 36, 34), seed=10), 5e-3, noslip=True)
+    s = check_residual(case)
+    Qref, dts = oracle_run(case, 3)
+    s.rk_step(3)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    assert ok, rep
