@@ -182,6 +182,42 @@ def bench_flux_variants(workload, n, variant, steps=5, warmup=2):
     return out
 
 
+def bench_navier_stokes(workload, n, variant, steps=5, warmup=2, reynolds=1.0e4):
+    """Same workload and tiles as the headline with the laminar viscous terms
+    switched on (mu = M / Re per unit length): whole RK steps timed with
+    events on the library stream (captured step), against the Euler step; the
+    paper reports the Navier-Stokes/Euler throughput ratio (about 0.7)."""
+    import torch
+
+    from paper_2012_02925_amd.solver import Solver
+
+    out = {"workload": "%s_%d" % (workload, n), "reynolds_per_unit_length": reynolds}
+    for label, visc in (("euler", False), ("navier_stokes", True)):
+        case = make_case(workload, n)
+        if visc:
+            mach = float(case.meta.get("mach", 0.8))
+            case.scheme.viscosity = mach / reynolds
+            out["viscosity"] = case.scheme.viscosity
+        s = Solver.from_case(case, device="cuda:0")
+        s.set_variant(variant)
+        s.rk_step(warmup)
+        st = s.stream  # the library's stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        s.rk_step(steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[label + "_ms_per_step"] = ms
+        out[label + "_cell_updates_per_s"] = case.ncells * case.scheme.rk_stages / (ms * 1e-3)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    out["ns_over_euler_throughput"] = out["euler_ms_per_step"] / out["navier_stokes_ms_per_step"]
+    return out
+
+
 def bench_adjoint(n=512, steps=50, every=10):
     """2D ramp n x n, van Albada (eps 1e-2), Roe, RK4 with the CFL step of the
     initial state held fixed; objective = integrated wall pressure after
@@ -363,6 +399,8 @@ def main():
         out["adjoint"] = bench_adjoint()
         print("[bench] face-flux variants on the same workload", file=sys.stderr, flush=True)
         out["flux_variants"] = bench_flux_variants(args.workload, args.n, out["config"]["tile_variant"])
+        print("[bench] laminar Navier-Stokes vs Euler on the same workload", file=sys.stderr, flush=True)
+        out["navier_stokes"] = bench_navier_stokes(args.workload, args.n, out["config"]["tile_variant"])
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

@@ -474,8 +474,9 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     fcursor = align_ll(fcursor + 14 + (nfb - 1) * B.vstride + padded, 16);
     B.corigin = 0;
     if (c->viscous) {
+      // centre coordinates, temperature, dim x (dim+1) viscous face fluxes
       B.corigin = ccursor + 14 + K;
-      ccursor = align_ll(ccursor + 14 + (dim - 1) * B.vstride + padded, 16);
+      ccursor = align_ll(ccursor + 14 + ((dim + 1) * (dim + 1) - 1) * B.vstride + padded, 16);
     }
     B.lorigin = 0;
     if (c->freezing) {
@@ -925,8 +926,7 @@ static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s) {
   if (st != CFD_OK || !c->viscous) return st;
   ViscArgs v = visc_args(c, q);
   const int nb = (int)c->blocks.size();
-  HIP_TRY(c, launch_pseudo_nodes(c->dim, v, 1, c->max_nodes, nb, s));
-  HIP_TRY(c, launch_viscous(c->dim, v, c->max_cells, nb, s));
+  HIP_TRY(c, launch_viscous(c->dim, v, c->max_padded, c->max_nodes, c->max_cells, nb, s));
   return CFD_OK;
 }
 

@@ -7,9 +7,9 @@
 // boundary the interior centre mirrored in the boundary face's plane), and
 // pseudo-node positions (mean centre of the interior and face-ghost cells
 // around each grid node).  Per stage: pseudo-node values of (u.., T) with
-// T = gamma p / rho, then per cell the Green's-theorem gradient on each of its
-// faces over the face's dual volume (the two cell centres and the face's
-// pseudo-nodes), the Stokes stresses, Theta = u . tau + k grad T and
+// T = gamma p / rho, then once per face the Green's-theorem gradient over the
+// face's dual volume (the two cell centres and the face's pseudo-nodes), the
+// Stokes stresses, Theta = u . tau + k grad T and F_v . S, and per cell
 // Rv = (1/Omega) sum F_v . S_out, which the stage kernel subtracts from the
 // inviscid residual.
 #pragma once
@@ -27,7 +27,8 @@ struct ViscArgs {
   const ChunkDev* chunks;  // ghost-fill chunk list 1 (transfer packs and physical patches)
   const double* nodes;     // grid nodes [coord][node]
   const double* metric;
-  double* centers;         // padded cell centres: dim arrays per block from BlockDev::corigin
+  double* centers;         // padded arrays from BlockDev::corigin: dim cell-centre coordinates,
+                           // the temperature, then dim * (dim+1) viscous face fluxes
   double* npos;            // pseudo-node positions [coord][node]
   double* nval;            // pseudo-node values [(u.., T)][node]
   const double* q;         // primitive state buffer, face ghosts filled
@@ -41,6 +42,10 @@ hipError_t launch_cell_centers(int dim, const ViscArgs& a, long long max_cells, 
 hipError_t launch_ghost_centers(int dim, const ViscArgs& a, int nchunks, hipStream_t s);
 // mode 0: pseudo-node positions from the centres; 1: values from the state
 hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, int mode, long long max_nodes, int nblocks, hipStream_t s);
-hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_cells, int nblocks, hipStream_t s);
+// Per stage: temperatures, pseudo-node values, face fluxes (each face once),
+// divergence into rv.  max_padded bounds (ni+2)(nj+2)(nk+2), max_nodes the
+// node count of a block.
+hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_padded, long long max_nodes, long long max_cells,
+                          int nblocks, hipStream_t s);
 
 }  // namespace cfd

@@ -13,13 +13,20 @@ __device__ __forceinline__ long long node_index(const BlockDev& B, int i, int j,
   return B.node0 + ((long long)k * (B.nj + 1) + j) * (long long)(B.ni + 1) + i;
 }
 
-__device__ __forceinline__ bool cell_coords(const BlockDev& B, long long c, int& i, int& j, int& k) {
-  if (c >= (long long)B.ni * B.nj * B.nk) return false;
-  i = (int)(c % B.ni);
-  const long long r = c / B.ni;
-  j = (int)(r % B.nj);
-  k = (int)(r / B.nj);
+// Index decode in 32-bit arithmetic (a block holds fewer than 2^31 cells and
+// nodes; 64-bit division would dominate these light kernels).
+__device__ __forceinline__ bool decode3(long long n, int e0, int e1, int e2, int& a0, int& a1, int& a2) {
+  if (n >= (long long)e0 * e1 * e2) return false;
+  const unsigned u = (unsigned)n;
+  const unsigned r = u / (unsigned)e0;
+  a0 = (int)(u - r * (unsigned)e0);
+  a2 = (int)(r / (unsigned)e1);
+  a1 = (int)(r - (unsigned)a2 * (unsigned)e1);
   return true;
+}
+
+__device__ __forceinline__ bool cell_coords(const BlockDev& B, long long c, int& i, int& j, int& k) {
+  return decode3(c, B.ni, B.nj, B.nk, i, j, k);
 }
 
 // Mean of the 2 (2D) or 4 (3D) nodes of the boundary face `face` of block B
@@ -140,11 +147,8 @@ __global__ void __launch_bounds__(256) pseudo_nodes_kernel(ViscArgs a, int mode)
   constexpr int NW = DIM + 1;
   const BlockDev B = a.blocks[blockIdx.y];
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int ei = B.ni + 1, ej = B.nj + 1;
-  if (n >= (long long)ei * ej * (DIM == 3 ? B.nk + 1 : 1)) return;
-  const int I = (int)(n % ei);
-  const long long r = n / ei;
-  const int J = (int)(r % ej), K = DIM == 3 ? (int)(r / ej) : 0;
+  int I, J, K;
+  if (!decode3(n, B.ni + 1, B.nj + 1, DIM == 3 ? B.nk + 1 : 1, I, J, K)) return;
   const int nw = mode == 0 ? DIM : DIM + 1;
   double acc[NW];
 #pragma unroll
@@ -169,7 +173,7 @@ __global__ void __launch_bounds__(256) pseudo_nodes_kernel(ViscArgs a, int mode)
           const double* q = a.q + B.origin + p;
 #pragma unroll
           for (int c = 0; c < DIM; ++c) acc[c] += q[(1 + c) * B.vstride];
-          acc[DIM] += a.gamma * q[(DIM + 1) * B.vstride] / q[0];
+          acc[DIM] += a.centers[B.corigin + DIM * B.vstride + p];
         }
       }
   const long long nn = node_index(B, I, J, K);
@@ -177,80 +181,79 @@ __global__ void __launch_bounds__(256) pseudo_nodes_kernel(ViscArgs a, int mode)
   for (int w = 0; w < nw; ++w) out[w * B.nnode_total + nn] = acc[w] / (double)cnt;
 }
 
-// Green's-theorem gradient of (u.., T) on one face from its dual volume:
-// cell centres CL, CR with values VL, VR and the face's pseudo-nodes P[m]
-// with values W[m] (2 in 2D, 4 in cyclic order in 3D).  G[v][x] = dV_v/dx.
+// Temperature T = gamma p / rho of every interior and face-ghost cell (array
+// DIM of the centre buffer), so each cell divides once per stage.
 template <int DIM>
-__device__ void dual_gradient(const double* CL, const double* CR, const double* VL, const double* VR,
-                              const double (*P)[DIM], const double (*W)[DIM + 1], double (*G)[DIM]) {
+__global__ void __launch_bounds__(256) temperature_kernel(ViscArgs a) {
+  const BlockDev B = a.blocks[blockIdx.y];
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!decode3(n, B.ni + 2, B.nj + 2, DIM == 3 ? B.nk + 2 : 1, i, j, k)) return;
+  i -= 1;
+  j -= 1;
+  if (DIM == 3) k -= 1;
+  const int out = (i < 0 || i >= B.ni) + (j < 0 || j >= B.nj) + (DIM == 3 ? (k < 0 || k >= B.nk) : 0);
+  if (out > 1) return;
+  const long long p = pidx(B, i, j, k);
+  const double* q = a.q + B.origin + p;
+  a.centers[B.corigin + DIM * B.vstride + p] = a.gamma * q[(DIM + 1) * B.vstride] / q[0];
+}
+
+// Green's-theorem gradient of (u.., T) on one face over its dual volume: the
+// cell centres CL, CR (values VL, VR) and the face's pseudo-nodes P[m]
+// (values W[m]; 2 in 2D, 4 in cyclic order in 3D), vertex values averaged
+// along each edge (2D) or over each triangle (3D).  Summed out, the surface
+// integral collapses to the closed "diamond" forms evaluated here (D = CR - CL):
+//   2D: G = [(V_R - V_L) rot(P1 - P0) + (W0 - W1) rot(D)] / (D x (P1 - P0)),
+//       rot(v) = (v_y, -v_x);
+//   3D: G = [A (V_R - V_L) - (D x e0)(W0 - W2)/2 - (D x e1)(W1 - W3)/2] / (D . A),
+//       e0 = P1 - P3, e1 = P2 - P0, A = e0 x e1 / 2 (D . A is three times the
+//       dual volume).
+template <int DIM>
+__device__ __forceinline__ void dual_gradient(const double* D, const double* VL, const double* VR,
+                                              const double (*P)[DIM], const double (*W)[DIM + 1],
+                                              double (*G)[DIM]) {
   constexpr int NW = DIM + 1;
-#pragma unroll
-  for (int v = 0; v < NW; ++v)
-#pragma unroll
-    for (int x = 0; x < DIM; ++x) G[v][x] = 0.0;
   if constexpr (DIM == 2) {
-    const double* pos[4] = {CL, P[0], CR, P[1]};
-    const double* val[4] = {VL, W[0], VR, W[1]};
-    double A = 0.0;
+    const double ex = P[1][0] - P[0][0], ey = P[1][1] - P[0][1];
+    const double inv = 1.0 / (D[0] * ey - D[1] * ex);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const double* pa = pos[k];
-      const double* pb = pos[(k + 1) % 4];
-      A += 0.5 * (pa[0] * pb[1] - pb[0] * pa[1]);
-      const double mx = pb[1] - pa[1], my = -(pb[0] - pa[0]);
-#pragma unroll
-      for (int v = 0; v < NW; ++v) {
-        const double avg = 0.5 * (val[k][v] + val[(k + 1) % 4][v]);
-        G[v][0] += avg * mx;
-        G[v][1] += avg * my;
-      }
+    for (int v = 0; v < NW; ++v) {
+      const double dv = VR[v] - VL[v], dw = W[0][v] - W[1][v];
+      G[v][0] = (dv * ey + dw * D[1]) * inv;
+      G[v][1] = (-dv * ex - dw * D[0]) * inv;
     }
-#pragma unroll
-    for (int v = 0; v < NW; ++v)
-#pragma unroll
-      for (int x = 0; x < DIM; ++x) G[v][x] /= A;
   } else {
-    double V = 0.0;
+    double e0[3], e1[3], A[3], b0[3], b1[3];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int kb = (k + 1) % 4;
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        // (CR, P_k, P_k+1) and (CL, P_k+1, P_k)
-        const double* pc = side == 0 ? CR : CL;
-        const double* p1 = side == 0 ? P[k] : P[kb];
-        const double* p2 = side == 0 ? P[kb] : P[k];
-        const double* vc = side == 0 ? VR : VL;
-        const double* v1 = side == 0 ? W[k] : W[kb];
-        const double* v2 = side == 0 ? W[kb] : W[k];
-        const double e1[3] = {p1[0] - pc[0], p1[1] - pc[1], p1[2] - pc[2]};
-        const double e2[3] = {p2[0] - pc[0], p2[1] - pc[1], p2[2] - pc[2]};
-        const double S[3] = {0.5 * (e1[1] * e2[2] - e1[2] * e2[1]), 0.5 * (e1[2] * e2[0] - e1[0] * e2[2]),
-                             0.5 * (e1[0] * e2[1] - e1[1] * e2[0])};
-        double cdot = 0.0;
-#pragma unroll
-        for (int x = 0; x < 3; ++x) cdot += ((pc[x] + p1[x] + p2[x]) / 3.0) * S[x];
-        V += cdot / 3.0;
-#pragma unroll
-        for (int v = 0; v < NW; ++v) {
-          const double avg = (vc[v] + v1[v] + v2[v]) / 3.0;
-#pragma unroll
-          for (int x = 0; x < 3; ++x) G[v][x] += avg * S[x];
-        }
-      }
+    for (int x = 0; x < 3; ++x) {
+      e0[x] = P[1][x] - P[3][x];
+      e1[x] = P[2][x] - P[0][x];
     }
+    A[0] = 0.5 * (e0[1] * e1[2] - e0[2] * e1[1]);
+    A[1] = 0.5 * (e0[2] * e1[0] - e0[0] * e1[2]);
+    A[2] = 0.5 * (e0[0] * e1[1] - e0[1] * e1[0]);
+    b0[0] = 0.5 * (D[1] * e0[2] - D[2] * e0[1]);
+    b0[1] = 0.5 * (D[2] * e0[0] - D[0] * e0[2]);
+    b0[2] = 0.5 * (D[0] * e0[1] - D[1] * e0[0]);
+    b1[0] = 0.5 * (D[1] * e1[2] - D[2] * e1[1]);
+    b1[1] = 0.5 * (D[2] * e1[0] - D[0] * e1[2]);
+    b1[2] = 0.5 * (D[0] * e1[1] - D[1] * e1[0]);
+    const double inv = 1.0 / (D[0] * A[0] + D[1] * A[1] + D[2] * A[2]);
 #pragma unroll
-    for (int v = 0; v < NW; ++v)
+    for (int v = 0; v < NW; ++v) {
+      const double dv = VR[v] - VL[v], d02 = W[0][v] - W[2][v], d13 = W[1][v] - W[3][v];
 #pragma unroll
-      for (int x = 0; x < DIM; ++x) G[v][x] /= V;
+      for (int x = 0; x < 3; ++x) G[v][x] = (A[x] * dv - b0[x] * d02 - b1[x] * d13) * inv;
+    }
   }
 }
 
 // Viscous flux F_v . S (momentum.., energy) from the face gradient G, the face
 // velocity uf and the area vector S.
 template <int DIM>
-__device__ void viscous_flux(const double (*G)[DIM], const double* uf, const double* S, double mu, double kcond,
-                             double* F) {
+__device__ __forceinline__ void viscous_flux(const double (*G)[DIM], const double* uf, const double* S, double mu,
+                                             double kcond, double* F) {
   double div = 0.0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) div += G[i][i];
@@ -278,73 +281,89 @@ __device__ void viscous_flux(const double (*G)[DIM], const double* uf, const dou
   F[DIM] = energy;
 }
 
+// Each face once: thread (i, j, k) over the cells and first high ghosts
+// computes the low face of direction d of cell (i, j, k) where that face
+// exists (index along d in 0..n_d, interior along the others) and stores
+// F_v . S in the face arrays (centre buffer, array DIM + 1 + d * (DIM+1) + v).
 template <int DIM>
-__device__ __forceinline__ void cell_values(const ViscArgs& a, const BlockDev& B, long long p, double gamma, double* V) {
-  const double* q = a.q + B.origin + p;
-#pragma unroll
-  for (int c = 0; c < DIM; ++c) V[c] = q[(1 + c) * B.vstride];
-  V[DIM] = gamma * q[(DIM + 1) * B.vstride] / q[0];
-}
-
-template <int DIM>
-__global__ void __launch_bounds__(256) viscous_kernel(ViscArgs a) {
+__global__ void __launch_bounds__(256) viscous_faces_kernel(ViscArgs a) {
   using ML = MetricLayout<DIM>;
   constexpr int NW = DIM + 1;
   constexpr int NP = DIM == 3 ? 4 : 2;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!decode3(n, B.ni + 1, B.nj + 1, DIM == 3 ? B.nk + 1 : 1, i, j, k)) return;
+  const long long vs = B.vstride;
+  const double* met = a.metric + B.morigin;
+  const double* cen = a.centers + B.corigin;
+  const long long pr = pidx(B, i, j, k);
+#pragma unroll 1
+  for (int d = 0; d < DIM; ++d) {
+    const bool ok = (d == 0 || i < B.ni) && (d == 1 || j < B.nj) && (DIM == 2 || d == 2 || k < B.nk);
+    if (!ok) continue;
+    const int di = d == 0, dj = d == 1, dk = d == 2;
+    const long long pl = pidx(B, i - di, j - dj, k - dk);
+    double D[DIM], VL[NW], VR[NW], S[DIM];
+#pragma unroll
+    for (int x = 0; x < DIM; ++x) {
+      D[x] = cen[x * vs + pr] - cen[x * vs + pl];
+      S[x] = met[ML::S(d, x) * vs + pr];
+      VL[x] = a.q[B.origin + (1 + x) * vs + pl];
+      VR[x] = a.q[B.origin + (1 + x) * vs + pr];
+    }
+    VL[DIM] = cen[DIM * vs + pl];
+    VR[DIM] = cen[DIM * vs + pr];
+    double P[NP][DIM], W[NP][NW];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+      // cyclic order over the tangential offsets (o1, o2): (0,0) (1,0) (1,1) (0,1),
+      // tangential axes in increasing order
+      const int o1 = (m == 1 || m == 2) ? 1 : 0, o2 = m >= 2 ? 1 : 0;
+      const int ni_ = i + (d == 0 ? 0 : o1);
+      const int nj_ = j + (d == 0 ? o1 : (d == 1 ? 0 : o2));
+      const int nk_ = DIM == 3 ? k + (d == 2 ? 0 : o2) : 0;
+      const long long nn = node_index(B, ni_, nj_, nk_);
+#pragma unroll
+      for (int x = 0; x < DIM; ++x) P[m][x] = a.npos[x * B.nnode_total + nn];
+#pragma unroll
+      for (int v = 0; v < NW; ++v) W[m][v] = a.nval[v * B.nnode_total + nn];
+    }
+    double G[NW][DIM], uf[DIM], F[NW];
+    dual_gradient<DIM>(D, VL, VR, P, W, G);
+#pragma unroll
+    for (int x = 0; x < DIM; ++x) uf[x] = 0.5 * (VL[x] + VR[x]);
+    viscous_flux<DIM>(G, uf, S, a.mu, a.kcond, F);
+    double* fo = a.centers + B.corigin + (DIM + 1 + d * NW) * vs + pr;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) fo[v * vs] = F[v];
+  }
+}
+
+// Rv = (1/Omega) sum_d (F_d(high face) - F_d(low face)), packed per cell.
+template <int DIM>
+__global__ void __launch_bounds__(256) viscous_divergence_kernel(ViscArgs a) {
+  using ML = MetricLayout<DIM>;
+  constexpr int NW = DIM + 1;
   const BlockDev B = a.blocks[blockIdx.y];
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   int i, j, k;
   if (!cell_coords(B, c, i, j, k)) return;
   const long long vs = B.vstride;
-  const double* met = a.metric + B.morigin;
-  double acc[NW];
+  const long long p = pidx(B, i, j, k);
+  const double* f = a.centers + B.corigin + (DIM + 1) * vs + p;
+  const long long step[3] = {1, B.pi, (long long)B.pi * B.pj};
+  const double iv = a.metric[B.morigin + ML::INVVOL * vs + p];
 #pragma unroll
-  for (int v = 0; v < NW; ++v) acc[v] = 0.0;
-  // one face at a time (loops not unrolled) keeps a single face's dual volume live
-#pragma unroll 1
-  for (int d = 0; d < DIM; ++d) {
-#pragma unroll 1
-    for (int s = 0; s < 2; ++s) {
-      // face index f = idx_d + s along d; cells f-1 (L) and f (R)
-      const int di = d == 0, dj = d == 1, dk = d == 2;
-      const int ri = i + di * s, rj = j + dj * s, rk = k + dk * s;
-      const long long pr = pidx(B, ri, rj, rk), pl = pidx(B, ri - di, rj - dj, rk - dk);
-      double CL[DIM], CR[DIM], VL[NW], VR[NW], S[DIM];
+  for (int v = 0; v < NW; ++v) {
+    double acc = 0.0;
 #pragma unroll
-      for (int x = 0; x < DIM; ++x) {
-        CL[x] = a.centers[B.corigin + x * vs + pl];
-        CR[x] = a.centers[B.corigin + x * vs + pr];
-        S[x] = met[ML::S(d, x) * vs + pr];
-      }
-      cell_values<DIM>(a, B, pl, a.gamma, VL);
-      cell_values<DIM>(a, B, pr, a.gamma, VR);
-      double P[NP][DIM], W[NP][NW];
-#pragma unroll
-      for (int m = 0; m < NP; ++m) {
-        // cyclic order over the tangential offsets (o1, o2): (0,0) (1,0) (1,1) (0,1),
-        // tangential axes in increasing order
-        const int o1 = (m == 1 || m == 2) ? 1 : 0, o2 = m >= 2 ? 1 : 0;
-        const int ni_ = ri + (d == 0 ? 0 : o1);
-        const int nj_ = rj + (d == 0 ? o1 : (d == 1 ? 0 : o2));
-        const int nk_ = DIM == 3 ? rk + (d == 2 ? 0 : o2) : 0;
-        const long long nn = node_index(B, ni_, nj_, nk_);
-#pragma unroll
-        for (int x = 0; x < DIM; ++x) P[m][x] = a.npos[x * B.nnode_total + nn];
-#pragma unroll
-        for (int v = 0; v < NW; ++v) W[m][v] = a.nval[v * B.nnode_total + nn];
-      }
-      double G[NW][DIM], uf[DIM], F[NW];
-      dual_gradient<DIM>(CL, CR, VL, VR, P, W, G);
-#pragma unroll
-      for (int x = 0; x < DIM; ++x) uf[x] = 0.5 * (VL[x] + VR[x]);
-      viscous_flux<DIM>(G, uf, S, a.mu, a.kcond, F);
-#pragma unroll
-      for (int v = 0; v < NW; ++v) acc[v] += s ? F[v] : -F[v];
+    for (int d = 0; d < DIM; ++d) {
+      const double* fd = f + (d * NW + v) * vs;
+      acc += fd[step[d]] - fd[0];
     }
+    a.rv[v * B.ncell_total + B.packed + c] = acc * iv;
   }
-  const double iv = met[ML::INVVOL * vs + pidx(B, i, j, k)];
-#pragma unroll
-  for (int v = 0; v < NW; ++v) a.rv[v * B.ncell_total + B.packed + c] = acc[v] * iv;
 }
 
 dim3 grid_of(long long items, int nblocks) { return dim3((unsigned)((items + 255) / 256), (unsigned)nblocks); }
@@ -376,11 +395,19 @@ hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, int mode, long long m
   return hipGetLastError();
 }
 
-hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_cells, int nblocks, hipStream_t s) {
-  if (dim == 2)
-    hipLaunchKernelGGL(viscous_kernel<2>, grid_of(max_cells, nblocks), dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(viscous_kernel<3>, grid_of(max_cells, nblocks), dim3(256), 0, s, a);
+hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_padded, long long max_nodes, long long max_cells,
+                          int nblocks, hipStream_t s) {
+  if (dim == 2) {
+    hipLaunchKernelGGL(temperature_kernel<2>, grid_of(max_padded, nblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pseudo_nodes_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a, 1);
+    hipLaunchKernelGGL(viscous_faces_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(viscous_divergence_kernel<2>, grid_of(max_cells, nblocks), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(temperature_kernel<3>, grid_of(max_padded, nblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(pseudo_nodes_kernel<3>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a, 1);
+    hipLaunchKernelGGL(viscous_faces_kernel<3>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(viscous_divergence_kernel<3>, grid_of(max_cells, nblocks), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
