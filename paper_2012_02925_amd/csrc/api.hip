@@ -112,7 +112,8 @@ struct cfd_ctx {
   size_t off_dtloc = 0, off_normpart = 0;
   bool viscous = false;   // laminar Navier-Stokes (cfg.viscosity > 0)
   long long center_doubles = 0;
-  size_t off_centers = 0, off_npos = 0, off_nval = 0, off_rv = 0;
+  size_t off_centers = 0, off_npos = 0, off_nval = 0, off_rv = 0, off_vistiles = 0;
+  std::vector<TileDev> vis_tiles;  // tiles of the fused 3D viscous pass
   bool freezing = false;  // workspace holds frozen-limiter arrays (cfd_enable_limiter_freezing)
   bool frozen = false;    // stage kernels use the frozen factors
   long long phi_doubles = 0;
@@ -632,6 +633,16 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   if (c->cfg.dt_mode == CFD_DT_LOCAL) c->off_dtloc = take((size_t)c->ncells * 8);
   if (c->freezing) c->off_phi = take((size_t)c->phi_doubles * 8);
   if (c->viscous) {
+    c->vis_tiles.clear();
+    if (dim == 3) {
+      int vx, vy, vk;
+      viscous_tile_shape(&vx, &vy, &vk);
+      for (int b = 0; b < nb; ++b)
+        for (int k0 = 0; k0 < c->blocks[b].nk; k0 += vk)
+          for (int j0 = 0; j0 < c->blocks[b].nj; j0 += vy)
+            for (int i0 = 0; i0 < c->blocks[b].ni; i0 += vx) c->vis_tiles.push_back(TileDev{b, i0, j0, k0});
+    }
+    c->off_vistiles = take(std::max<size_t>(c->vis_tiles.size(), 1) * sizeof(TileDev));
     c->off_centers = take((size_t)c->center_doubles * 8);
     c->off_npos = take((size_t)c->nnodes * dim * 8);
     c->off_nval = take((size_t)c->nnodes * (dim + 1) * 8);
@@ -756,6 +767,8 @@ static ViscArgs visc_args(cfd_ctx* c, const double* q) {
   v.mu = c->cfg.viscosity;
   v.kcond = c->cfg.viscosity > 0.0 ? c->cfg.viscosity / ((c->cfg.gamma - 1.0) * c->cfg.prandtl) : 0.0;
   v.gamma = c->cfg.gamma;
+  v.tiles = c->dptr<TileDev>(c->off_vistiles);
+  v.ntiles = (int)c->vis_tiles.size();
   return v;
 }
 
@@ -824,6 +837,7 @@ extern "C" cfd_status cfd_bind_workspace(cfd_ctx* c, void* ptr, size_t bytes) {
     if ((s = upload(c, c->off_walllist, c->wall_list)) != CFD_OK) return s;
     HIP_TRY(c, hipMemsetAsync(c->ws + c->off_stD, 0, c->off_G - c->off_stD, c->stream));
   }
+  if (c->viscous && (s = upload(c, c->off_vistiles, c->vis_tiles)) != CFD_OK) return s;
   // nodes: [coord][concatenated nodes]
   std::vector<double> nodes((size_t)c->nnodes * c->dim);
   for (size_t b = 0; b < c->hblocks.size(); ++b) {

@@ -366,6 +366,224 @@ __global__ void __launch_bounds__(256) viscous_divergence_kernel(ViscArgs a) {
   }
 }
 
+// Fused 3D pass over a tile of VT_X x VT_Y columns and up to VT_K planes:
+// the plane pair (k, k+1) of cells (with a one-cell halo ring) and of
+// pseudo-nodes is staged in LDS while the tile marches in k; every face of
+// the tile is computed once (x- and y-faces into LDS, the column's k-faces in
+// registers) and each cell writes its Rv.  Same arithmetic as the per-face
+// kernels above, without their repeated global reads.
+constexpr int VT_X = 16, VT_Y = 8, VT_K = 32;
+
+__global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
+  using ML = MetricLayout<3>;
+  constexpr int NT = VT_X * VT_Y;
+  constexpr int CX = VT_X + 2, CY = VT_Y + 2, NC = CX * CY;  // cells i0-1..i0+VT_X, j0-1..j0+VT_Y
+  constexpr int NXn = VT_X + 1, NYn = VT_Y + 1, NN = NXn * NYn;
+  constexpr int NFX = NXn * VT_Y, NFY = VT_X * NYn;
+  // cell data: 0-2 centre, 3-5 velocity, 6 temperature; node data: 0-2 position, 3-6 values
+  __shared__ double sc[2][7][NC];
+  __shared__ double sn[2][7][NN];
+  __shared__ double fx[4][NFX];
+  __shared__ double fy[4][NFY];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % VT_X, ty = tid / VT_X;
+  const TileDev tile = a.tiles[blockIdx.x];
+  const BlockDev B = a.blocks[tile.block];
+  const int i0 = tile.i0, j0 = tile.j0, k0 = tile.k0;
+  const int k1 = min(k0 + VT_K, B.nk);
+  const long long vs = B.vstride;
+  const double* met = a.metric + B.morigin;
+  const double* cen = a.centers + B.corigin;
+  const double* q = a.q + B.origin;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool own = i < B.ni && j < B.nj;
+
+  // The next plane's cells and node positions are fetched into registers
+  // while the current plane's faces are computed (2 items per thread each).
+  constexpr int HC = (NC + NT - 1) / NT, HN = (NN + NT - 1) / NT;
+  double pc[HC][8];  // centre, velocity, rho, p
+  bool pv[HC];
+  double pn[HN][3];
+  auto fetch_cells = [&](int kk) {
+#pragma unroll
+    for (int h = 0; h < HC; ++h) {
+      const int e = tid + h * NT;
+      const int ii = i0 - 1 + e % CX, jj = j0 - 1 + e / CX;
+      const int out = (ii < 0 || ii >= B.ni) + (jj < 0 || jj >= B.nj) + (kk < 0 || kk >= B.nk);
+      pv[h] = e < NC && ii <= B.ni && jj <= B.nj && out <= 1;
+      if (pv[h]) {
+        const long long p = pidx(B, ii, jj, kk);
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          pc[h][x] = cen[x * vs + p];
+          pc[h][3 + x] = q[(1 + x) * vs + p];
+        }
+        pc[h][6] = q[p];
+        pc[h][7] = q[4 * vs + p];
+      }
+    }
+  };
+  auto store_cells = [&](int slot) {
+#pragma unroll
+    for (int h = 0; h < HC; ++h) {
+      const int e = tid + h * NT;
+      if (e >= NC) continue;
+#pragma unroll
+      for (int w = 0; w < 6; ++w) sc[slot][w][e] = pv[h] ? pc[h][w] : 0.0;
+      sc[slot][6][e] = pv[h] ? a.gamma * pc[h][7] / pc[h][6] : 0.0;
+    }
+  };
+  auto fetch_node_pos = [&](int K) {
+#pragma unroll
+    for (int h = 0; h < HN; ++h) {
+      const int e = tid + h * NT;
+      const int I = i0 + e % NXn, J = j0 + e / NXn;
+      if (e < NN && I <= B.ni && J <= B.nj) {
+        const long long nn = node_index(B, I, J, K);
+#pragma unroll
+        for (int x = 0; x < 3; ++x) pn[h][x] = a.npos[x * B.nnode_total + nn];
+      }
+    }
+  };
+  // pseudo-nodes of node plane K from cell planes K-1 (slot sl) and K (slot sh)
+  auto make_nodes = [&](int K, int sl, int sh, int slot) {
+#pragma unroll
+    for (int h = 0; h < HN; ++h) {
+      const int e = tid + h * NT;
+      const int I = i0 + e % NXn, J = j0 + e / NXn;
+      if (e >= NN || I > B.ni || J > B.nj) continue;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      int cnt = 0;
+#pragma unroll
+      for (int ai = 0; ai < 2; ++ai)
+#pragma unroll
+        for (int aj = 0; aj < 2; ++aj)
+#pragma unroll
+          for (int ak = 0; ak < 2; ++ak) {
+            const int out = (ai == 0 ? I == 0 : I == B.ni) + (aj == 0 ? J == 0 : J == B.nj) + (ak == 0 ? K == 0 : K == B.nk);
+            if (out > 1) continue;
+            const int c = (J - j0 + aj) * CX + (I - i0 + ai);  // cell (I-1+ai, J-1+aj) in the halo frame
+            const int sls = ak ? sh : sl;
+            ++cnt;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc[w] += sc[sls][3 + w][c];
+          }
+#pragma unroll
+      for (int x = 0; x < 3; ++x) sn[slot][x][e] = pn[h][x];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) sn[slot][3 + w][e] = acc[w] / (double)cnt;
+    }
+  };
+  // viscous flux of one face: cells cl (slot sl), cr (slot sr); nodes m0..m3 with their slots
+  auto face = [&](int sl, int cl, int sr, int cr, const int* ns, const int* ne, const double* S, double* F) {
+    double D[3], VL[4], VR[4], P[4][3], W[4][4], G[4][3], uf[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) D[x] = sc[sr][x][cr] - sc[sl][x][cl];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      VL[w] = sc[sl][3 + w][cl];
+      VR[w] = sc[sr][3 + w][cr];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+      for (int x = 0; x < 3; ++x) P[m][x] = sn[ns[m]][x][ne[m]];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) W[m][w] = sn[ns[m]][3 + w][ne[m]];
+    }
+    dual_gradient<3>(D, VL, VR, P, W, G);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) uf[x] = 0.5 * (VL[x] + VR[x]);
+    viscous_flux<3>(G, uf, S, a.mu, a.kcond, F);
+  };
+  // k-face K of the own column: cells K-1 (slot sl) and K (slot sh), node plane K (slot sn_)
+  auto zface = [&](int K, int sl, int sh, int snk, double* F) {
+    const int c = (ty + 1) * CX + tx + 1;
+    const int n0 = ty * NXn + tx;
+    const int ns[4] = {snk, snk, snk, snk};
+    const int ne[4] = {n0, n0 + 1, n0 + NXn + 1, n0 + NXn};  // (i,j) (i+1,j) (i+1,j+1) (i,j+1)
+    double S[3];
+    const long long p = pidx(B, i, j, K);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) S[x] = met[ML::S(2, x) * vs + p];
+    face(sl, c, sh, c, ns, ne, S, F);
+  };
+
+  // prologue: cell planes k0-1 and k0, node plane k0, the first k-face
+  fetch_cells(k0 - 1);
+  store_cells(1);
+  fetch_cells(k0);
+  store_cells(0);
+  fetch_node_pos(k0);
+  __syncthreads();
+  make_nodes(k0, 1, 0, 0);
+  fetch_cells(k0 + 1);
+  fetch_node_pos(k0 + 1);
+  __syncthreads();
+  double fzlo[4] = {0.0, 0.0, 0.0, 0.0};
+  if (own) zface(k0, 1, 0, 0, fzlo);
+
+  for (int k = k0; k < k1; ++k) {
+    const int s0 = (k - k0) & 1, s1 = s0 ^ 1;  // slots of plane k and k+1
+    __syncthreads();  // slot s1 (plane k-1 and node plane k-1) is free
+    store_cells(s1);  // plane k+1, fetched during the previous plane
+    __syncthreads();
+    make_nodes(k + 1, s0, s1, s1);
+    __syncthreads();
+    if (k + 1 < k1) {  // plane k+2 and node plane k+2 while this plane's faces compute
+      fetch_cells(k + 2);
+      fetch_node_pos(k + 2);
+    }
+    // x-faces (I, j) and y-faces (i, J) of plane k
+    for (int e = tid; e < NFX; e += NT) {
+      const int I = i0 + e % NXn, jr = e / NXn, jj = j0 + jr;
+      if (I > B.ni || jj >= B.nj) continue;
+      const int cr = (jr + 1) * CX + (I - i0 + 1);
+      const int n0 = jr * NXn + (I - i0);
+      const int ns[4] = {s0, s0, s1, s1};
+      const int ne[4] = {n0, n0 + NXn, n0 + NXn, n0};  // (I,j,k) (I,j+1,k) (I,j+1,k+1) (I,j,k+1)
+      double S[3], F[4];
+      const long long p = pidx(B, I, jj, k);
+#pragma unroll
+      for (int x = 0; x < 3; ++x) S[x] = met[ML::S(0, x) * vs + p];
+      face(s0, cr - 1, s0, cr, ns, ne, S, F);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) fx[w][e] = F[w];
+    }
+    for (int e = tid; e < NFY; e += NT) {
+      const int ic = e % VT_X, J = j0 + e / VT_X, ii = i0 + ic;
+      if (ii >= B.ni || J > B.nj) continue;
+      const int cr = (J - j0 + 1) * CX + ic + 1;
+      const int n0 = (J - j0) * NXn + ic;
+      const int ns[4] = {s0, s0, s1, s1};
+      const int ne[4] = {n0, n0 + 1, n0 + 1, n0};  // (i,J,k) (i+1,J,k) (i+1,J,k+1) (i,J,k+1)
+      double S[3], F[4];
+      const long long p = pidx(B, ii, J, k);
+#pragma unroll
+      for (int x = 0; x < 3; ++x) S[x] = met[ML::S(1, x) * vs + p];
+      face(s0, cr - CX, s0, cr, ns, ne, S, F);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) fy[w][e] = F[w];
+    }
+    double fzhi[4];
+    if (own) zface(k + 1, s0, s1, s1, fzhi);
+    __syncthreads();
+    if (own) {
+      const long long p = pidx(B, i, j, k);
+      const double iv = met[ML::INVVOL * vs + p];
+      const long long cell = B.packed + ((long long)k * B.nj + j) * B.ni + i;
+      const int ex = ty * NXn + tx, ey = ty * VT_X + tx;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const double acc = (fx[w][ex + 1] - fx[w][ex]) + (fy[w][ey + VT_X] - fy[w][ey]) + (fzhi[w] - fzlo[w]);
+        a.rv[w * B.ncell_total + cell] = acc * iv;
+        fzlo[w] = fzhi[w];
+      }
+    }
+  }
+}
+
 dim3 grid_of(long long items, int nblocks) { return dim3((unsigned)((items + 255) / 256), (unsigned)nblocks); }
 
 }  // namespace
@@ -395,6 +613,12 @@ hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, int mode, long long m
   return hipGetLastError();
 }
 
+void viscous_tile_shape(int* tx, int* ty, int* tk) {
+  *tx = VT_X;
+  *ty = VT_Y;
+  *tk = VT_K;
+}
+
 hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_padded, long long max_nodes, long long max_cells,
                           int nblocks, hipStream_t s) {
   if (dim == 2) {
@@ -402,11 +626,8 @@ hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_padded, long
     hipLaunchKernelGGL(pseudo_nodes_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a, 1);
     hipLaunchKernelGGL(viscous_faces_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(viscous_divergence_kernel<2>, grid_of(max_cells, nblocks), dim3(256), 0, s, a);
-  } else {
-    hipLaunchKernelGGL(temperature_kernel<3>, grid_of(max_padded, nblocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(pseudo_nodes_kernel<3>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a, 1);
-    hipLaunchKernelGGL(viscous_faces_kernel<3>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(viscous_divergence_kernel<3>, grid_of(max_cells, nblocks), dim3(256), 0, s, a);
+  } else if (a.ntiles > 0) {
+    hipLaunchKernelGGL(viscous_tile_kernel, dim3(a.ntiles), dim3(VT_X * VT_Y), 0, s, a);
   }
   return hipGetLastError();
 }
