@@ -286,6 +286,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-extras", action="store_true", help="skip the batching and adjoint measurements")
+    ap.add_argument("--viscosity", type=float, default=0.0,
+                    help="profiling aid: run the measured workload with the laminar viscous terms (mu)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="run only the adjoint measurement and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -314,6 +316,9 @@ def main():
         print(json.dumps(bench_adjoint()))
         return
     case = make_case(args.workload, args.n)
+    if args.viscosity > 0.0:
+        case.scheme.viscosity = args.viscosity
+        case.name += "_navier_stokes"
     print("[bench] workload %s, %d cells, building" % (case.name, case.ncells), file=sys.stderr, flush=True)
     s = Solver.from_case(case, device="cuda:0")
     chosen = None

@@ -641,6 +641,8 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
         for (int k0 = 0; k0 < c->blocks[b].nk; k0 += vk)
           for (int j0 = 0; j0 < c->blocks[b].nj; j0 += vy)
             for (int i0 = 0; i0 < c->blocks[b].ni; i0 += vx) c->vis_tiles.push_back(TileDev{b, i0, j0, k0});
+      // neighbouring tiles share halo cache lines: keep them on one XCD's L2
+      c->vis_tiles = xcd_order(c->vis_tiles, 0, c->vis_tiles.size());
     }
     c->off_vistiles = take(std::max<size_t>(c->vis_tiles.size(), 1) * sizeof(TileDev));
     c->off_centers = take((size_t)c->center_doubles * 8);
