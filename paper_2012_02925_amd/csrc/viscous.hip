@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(256) viscous_divergence_kernel(ViscArgs a) {
 // the tile is computed once (x- and y-faces into LDS, the column's k-faces in
 // registers) and each cell writes its Rv.  Same arithmetic as the per-face
 // kernels above, without their repeated global reads.
-constexpr int VT_X = 16, VT_Y = 8, VT_K = 32;
+constexpr int VT_X = 16, VT_Y = 16, VT_K = 32;
 
 __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
   using ML = MetricLayout<3>;
@@ -380,9 +380,9 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
   constexpr int CX = VT_X + 2, CY = VT_Y + 2, NC = CX * CY;  // cells i0-1..i0+VT_X, j0-1..j0+VT_Y
   constexpr int NXn = VT_X + 1, NYn = VT_Y + 1, NN = NXn * NYn;
   constexpr int NFX = NXn * VT_Y, NFY = VT_X * NYn;
-  // cell data: 0-2 centre, 3-5 velocity, 6 temperature; node data: 0-2 position, 3-6 values
+  // cell data: 0-2 centre, 3-5 velocity, 6 temperature; node data: velocity, temperature
   __shared__ double sc[2][7][NC];
-  __shared__ double sn[2][7][NN];
+  __shared__ double sn[2][4][NN];  // pseudo-node values (positions are read from the set-up array)
   __shared__ double fx[4][NFX];
   __shared__ double fy[4][NFY];
 
@@ -399,12 +399,11 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
   const int i = i0 + tx, j = j0 + ty;
   const bool own = i < B.ni && j < B.nj;
 
-  // The next plane's cells and node positions are fetched into registers
-  // while the current plane's faces are computed (2 items per thread each).
+  // The next plane's cells are fetched into registers while the current
+  // plane's faces are computed (2 items per thread).
   constexpr int HC = (NC + NT - 1) / NT, HN = (NN + NT - 1) / NT;
   double pc[HC][8];  // centre, velocity, rho, p
   bool pv[HC];
-  double pn[HN][3];
   auto fetch_cells = [&](int kk) {
 #pragma unroll
     for (int h = 0; h < HC; ++h) {
@@ -434,18 +433,6 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
       sc[slot][6][e] = pv[h] ? a.gamma * pc[h][7] / pc[h][6] : 0.0;
     }
   };
-  auto fetch_node_pos = [&](int K) {
-#pragma unroll
-    for (int h = 0; h < HN; ++h) {
-      const int e = tid + h * NT;
-      const int I = i0 + e % NXn, J = j0 + e / NXn;
-      if (e < NN && I <= B.ni && J <= B.nj) {
-        const long long nn = node_index(B, I, J, K);
-#pragma unroll
-        for (int x = 0; x < 3; ++x) pn[h][x] = a.npos[x * B.nnode_total + nn];
-      }
-    }
-  };
   // pseudo-nodes of node plane K from cell planes K-1 (slot sl) and K (slot sh)
   auto make_nodes = [&](int K, int sl, int sh, int slot) {
 #pragma unroll
@@ -470,13 +457,13 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
             for (int w = 0; w < 4; ++w) acc[w] += sc[sls][3 + w][c];
           }
 #pragma unroll
-      for (int x = 0; x < 3; ++x) sn[slot][x][e] = pn[h][x];
-#pragma unroll
-      for (int w = 0; w < 4; ++w) sn[slot][3 + w][e] = acc[w] / (double)cnt;
+      for (int w = 0; w < 4; ++w) sn[slot][w][e] = acc[w] / (double)cnt;
     }
   };
-  // viscous flux of one face: cells cl (slot sl), cr (slot sr); nodes m0..m3 with their slots
-  auto face = [&](int sl, int cl, int sr, int cr, const int* ns, const int* ne, const double* S, double* F) {
+  // viscous flux of one face: cells cl (slot sl), cr (slot sr); nodes m0..m3:
+  // LDS slot ns, frame index ne (I - i0 + (J - j0) * NXn), node plane nkk
+  auto face = [&](int sl, int cl, int sr, int cr, const int* ns, const int* ne, const int* nkk, const double* S,
+                  double* F) {
     double D[3], VL[4], VR[4], P[4][3], W[4][4], G[4][3], uf[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x) D[x] = sc[sr][x][cr] - sc[sl][x][cl];
@@ -487,10 +474,11 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
+      const long long nn = node_index(B, i0 + ne[m] % NXn, j0 + ne[m] / NXn, nkk[m]);
 #pragma unroll
-      for (int x = 0; x < 3; ++x) P[m][x] = sn[ns[m]][x][ne[m]];
+      for (int x = 0; x < 3; ++x) P[m][x] = a.npos[x * B.nnode_total + nn];
 #pragma unroll
-      for (int w = 0; w < 4; ++w) W[m][w] = sn[ns[m]][3 + w][ne[m]];
+      for (int w = 0; w < 4; ++w) W[m][w] = sn[ns[m]][w][ne[m]];
     }
     dual_gradient<3>(D, VL, VR, P, W, G);
 #pragma unroll
@@ -502,12 +490,13 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     const int c = (ty + 1) * CX + tx + 1;
     const int n0 = ty * NXn + tx;
     const int ns[4] = {snk, snk, snk, snk};
+    const int nkk[4] = {K, K, K, K};
     const int ne[4] = {n0, n0 + 1, n0 + NXn + 1, n0 + NXn};  // (i,j) (i+1,j) (i+1,j+1) (i,j+1)
     double S[3];
     const long long p = pidx(B, i, j, K);
 #pragma unroll
     for (int x = 0; x < 3; ++x) S[x] = met[ML::S(2, x) * vs + p];
-    face(sl, c, sh, c, ns, ne, S, F);
+    face(sl, c, sh, c, ns, ne, nkk, S, F);
   };
 
   // prologue: cell planes k0-1 and k0, node plane k0, the first k-face
@@ -515,11 +504,9 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
   store_cells(1);
   fetch_cells(k0);
   store_cells(0);
-  fetch_node_pos(k0);
   __syncthreads();
   make_nodes(k0, 1, 0, 0);
   fetch_cells(k0 + 1);
-  fetch_node_pos(k0 + 1);
   __syncthreads();
   double fzlo[4] = {0.0, 0.0, 0.0, 0.0};
   if (own) zface(k0, 1, 0, 0, fzlo);
@@ -533,7 +520,6 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     __syncthreads();
     if (k + 1 < k1) {  // plane k+2 and node plane k+2 while this plane's faces compute
       fetch_cells(k + 2);
-      fetch_node_pos(k + 2);
     }
     // x-faces (I, j) and y-faces (i, J) of plane k
     for (int e = tid; e < NFX; e += NT) {
@@ -542,12 +528,13 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
       const int cr = (jr + 1) * CX + (I - i0 + 1);
       const int n0 = jr * NXn + (I - i0);
       const int ns[4] = {s0, s0, s1, s1};
+      const int nkk[4] = {k, k, k + 1, k + 1};
       const int ne[4] = {n0, n0 + NXn, n0 + NXn, n0};  // (I,j,k) (I,j+1,k) (I,j+1,k+1) (I,j,k+1)
       double S[3], F[4];
       const long long p = pidx(B, I, jj, k);
 #pragma unroll
       for (int x = 0; x < 3; ++x) S[x] = met[ML::S(0, x) * vs + p];
-      face(s0, cr - 1, s0, cr, ns, ne, S, F);
+      face(s0, cr - 1, s0, cr, ns, ne, nkk, S, F);
 #pragma unroll
       for (int w = 0; w < 4; ++w) fx[w][e] = F[w];
     }
@@ -557,12 +544,13 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
       const int cr = (J - j0 + 1) * CX + ic + 1;
       const int n0 = (J - j0) * NXn + ic;
       const int ns[4] = {s0, s0, s1, s1};
+      const int nkk[4] = {k, k, k + 1, k + 1};
       const int ne[4] = {n0, n0 + 1, n0 + 1, n0};  // (i,J,k) (i+1,J,k) (i+1,J,k+1) (i,J,k+1)
       double S[3], F[4];
       const long long p = pidx(B, ii, J, k);
 #pragma unroll
       for (int x = 0; x < 3; ++x) S[x] = met[ML::S(1, x) * vs + p];
-      face(s0, cr - CX, s0, cr, ns, ne, S, F);
+      face(s0, cr - CX, s0, cr, ns, ne, nkk, S, F);
 #pragma unroll
       for (int w = 0; w < 4; ++w) fy[w][e] = F[w];
     }
