@@ -442,3 +442,42 @@ def test_navier_stokes_3d(which):
     s.rk_step(3)
     ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
     assert ok, rep
+
+
+def _rotated_two_block_box(ni=20, nj=12, nk=10, cut=8, seed=9):
+    """The jittered periodic box cut at i = cut; the second block rotated
+    about the i axis (j' = k, k' = nj-1-j) and joined with orient 6 / 5, so
+    connections swap and reverse tangential axes."""
+    c = synth.jittered_periodic_box(dims=(ni, nj, nk), seed=seed)
+    X, q = c.blocks[0].nodes, c.prims[0]
+    XA, qA = X[:, :, :, :cut + 1].copy(), q[:, :, :, :cut].copy()
+    XB, qB = X[:, :, :, cut:], q[:, :, :, cut:]
+    XBr = XB.transpose(0, 2, 1, 3)[:, ::-1].copy()
+    qBr = qB.transpose(0, 2, 1, 3)[:, ::-1].copy()
+    nB = ni - cut
+    A = synth.Block(cut, nj, nk, XA)
+    B = synth.Block(nB, nk, nj, XBr)
+    conns = [synth.Connection(0, synth.IMAX, [0, 0], [nj, nk], 1, synth.IMIN, [0, 0], [nk, nj], 6),
+             synth.Connection(1, synth.IMAX, [0, 0], [nk, nj], 0, synth.IMIN, [0, 0], [nj, nk], 5),
+             synth.Connection(0, synth.JMIN, [0, 0], [cut, nk], 0, synth.JMAX, [0, 0], [cut, nk], 0),
+             synth.Connection(0, synth.KMIN, [0, 0], [cut, nj], 0, synth.KMAX, [0, 0], [cut, nj], 0),
+             synth.Connection(1, synth.JMIN, [0, 0], [nB, nj], 1, synth.JMAX, [0, 0], [nB, nj], 0),
+             synth.Connection(1, synth.KMIN, [0, 0], [nB, nk], 1, synth.KMAX, [0, 0], [nB, nk], 0)]
+    return synth.Case("rotated_two_block_box_%dx%dx%d" % (ni, nj, nk), 3, [A, B], [], conns, [qA, qBr],
+                      c.scheme, 1)
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_rotated_two_block_box_3d(viscous):
+    """Oriented 3D connections (axis swap and reversal): ghost exchange and,
+    with viscosity, the ghost cell centres and pseudo-nodes at block edges."""
+    _say("case: rotated two-block box, viscous", viscous)
+    case = _rotated_two_block_box()
+    if viscous:
+        case = _viscous(case, 0.01)
+    s = check_residual(case)
+    s.set_variant(1)
+    Qref, dts = oracle_run(case, 4)
+    s.rk_step(4)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    assert ok, rep
