@@ -182,6 +182,42 @@ def bench_flux_variants(workload, n, variant, steps=5, warmup=2):
     return out
 
 
+def bench_ramp(n=1024, steps=10, warmup=3):
+    """The 2D 1024^2 compression ramp (supersonic inflow, extrapolated outflow,
+    slip wall; van Leer + Roe, RK4): autotuned tiles, captured steps timed
+    with events on the library stream, and the stage kernel's mean launch
+    time from HIP events with its algorithmic HBM fraction."""
+    import torch
+
+    from paper_2012_02925_amd.solver import Solver
+
+    case = make_case("compression_ramp", n)
+    s = Solver.from_case(case, device="cuda:0")
+    v = s.autotune(reps=3)
+    s.rk_step(warmup)
+    st = s.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    s.rk_step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    s.profile(True)
+    s.rk_step(steps)
+    kms, launches = s.kernel_time()
+    s.profile(False)
+    kms /= max(launches, 1)
+    out = {"workload": case.name, "cells": case.ncells, "tile_variant": v, "ms_per_step": ms,
+           "cell_updates_per_s": case.ncells * case.scheme.rk_stages / (ms * 1e-3),
+           "stage_kernel_ms": kms,
+           "stage_kernel_hbm_frac": BYTES_PER_CELL_STAGE[2] * case.ncells / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_navier_stokes(workload, n, variant, steps=5, warmup=2, reynolds=1.0e4):
     """Same workload and tiles as the headline with the laminar viscous terms
     switched on (mu = M / Re per unit length): whole RK steps timed with
@@ -404,6 +440,8 @@ def main():
         out["adjoint"] = bench_adjoint()
         print("[bench] face-flux variants on the same workload", file=sys.stderr, flush=True)
         out["flux_variants"] = bench_flux_variants(args.workload, args.n, out["config"]["tile_variant"])
+        print("[bench] 2D 1024^2 compression ramp", file=sys.stderr, flush=True)
+        out["ramp_2d"] = bench_ramp()
         print("[bench] laminar Navier-Stokes vs Euler on the same workload", file=sys.stderr, flush=True)
         out["navier_stokes"] = bench_navier_stokes(args.workload, args.n, out["config"]["tile_variant"])
     if not args.no_cpu_baseline:

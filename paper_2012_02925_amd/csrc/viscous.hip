@@ -398,6 +398,12 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
   const double* q = a.q + B.origin;
   const int i = i0 + tx, j = j0 + ty;
   const bool own = i < B.ni && j < B.nj;
+  const int E = B.ni + 1;                              // node row pitch
+  const long long nplane = (long long)(B.nj + 1) * E;  // nodes per plane
+  const long long cplane = (long long)B.pj * B.pi;     // padded cells per plane
+  // 64-bit parts are per plane (uniform); the in-plane offsets stay 32-bit
+  auto node_base = [&](int K) { return node_index(B, i0, j0, K); };
+  auto cell_at = [&](int ii, int jj, int kk) { return (long long)kk * cplane + (jj * B.pi + ii); };
 
   // The next plane's cells are fetched into registers while the current
   // plane's faces are computed (2 items per thread).
@@ -412,7 +418,7 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
       const int out = (ii < 0 || ii >= B.ni) + (jj < 0 || jj >= B.nj) + (kk < 0 || kk >= B.nk);
       pv[h] = e < NC && ii <= B.ni && jj <= B.nj && out <= 1;
       if (pv[h]) {
-        const long long p = pidx(B, ii, jj, kk);
+        const long long p = cell_at(ii, jj, kk);
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
           pc[h][x] = cen[x * vs + p];
@@ -456,13 +462,14 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
 #pragma unroll
             for (int w = 0; w < 4; ++w) acc[w] += sc[sls][3 + w][c];
           }
+      const double rc = 1.0 / (double)cnt;
 #pragma unroll
-      for (int w = 0; w < 4; ++w) sn[slot][w][e] = acc[w] / (double)cnt;
+      for (int w = 0; w < 4; ++w) sn[slot][w][e] = acc[w] * rc;
     }
   };
   // viscous flux of one face: cells cl (slot sl), cr (slot sr); nodes m0..m3:
-  // LDS slot ns, frame index ne (I - i0 + (J - j0) * NXn), node plane nkk
-  auto face = [&](int sl, int cl, int sr, int cr, const int* ns, const int* ne, const int* nkk, const double* S,
+  // LDS slot ns, frame index ne (I - i0 + (J - j0) * NXn), global node index go
+  auto face = [&](int sl, int cl, int sr, int cr, const int* ns, const int* ne, const long long* go, const double* S,
                   double* F) {
     double D[3], VL[4], VR[4], P[4][3], W[4][4], G[4][3], uf[3];
 #pragma unroll
@@ -474,9 +481,8 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const long long nn = node_index(B, i0 + ne[m] % NXn, j0 + ne[m] / NXn, nkk[m]);
 #pragma unroll
-      for (int x = 0; x < 3; ++x) P[m][x] = a.npos[x * B.nnode_total + nn];
+      for (int x = 0; x < 3; ++x) P[m][x] = a.npos[x * B.nnode_total + go[m]];
 #pragma unroll
       for (int w = 0; w < 4; ++w) W[m][w] = sn[ns[m]][w][ne[m]];
     }
@@ -490,13 +496,14 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     const int c = (ty + 1) * CX + tx + 1;
     const int n0 = ty * NXn + tx;
     const int ns[4] = {snk, snk, snk, snk};
-    const int nkk[4] = {K, K, K, K};
     const int ne[4] = {n0, n0 + 1, n0 + NXn + 1, n0 + NXn};  // (i,j) (i+1,j) (i+1,j+1) (i,j+1)
+    const long long g0 = node_base(K) + (ty * E + tx);
+    const long long go[4] = {g0, g0 + 1, g0 + E + 1, g0 + E};
     double S[3];
-    const long long p = pidx(B, i, j, K);
+    const long long p = cell_at(i, j, K);
 #pragma unroll
     for (int x = 0; x < 3; ++x) S[x] = met[ML::S(2, x) * vs + p];
-    face(sl, c, sh, c, ns, ne, nkk, S, F);
+    face(sl, c, sh, c, ns, ne, go, S, F);
   };
 
   // prologue: cell planes k0-1 and k0, node plane k0, the first k-face
@@ -521,6 +528,7 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     if (k + 1 < k1) {  // plane k+2 and node plane k+2 while this plane's faces compute
       fetch_cells(k + 2);
     }
+    const long long nb0 = node_base(k);  // node (i0, j0, k)
     // x-faces (I, j) and y-faces (i, J) of plane k
     for (int e = tid; e < NFX; e += NT) {
       const int I = i0 + e % NXn, jr = e / NXn, jj = j0 + jr;
@@ -528,13 +536,14 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
       const int cr = (jr + 1) * CX + (I - i0 + 1);
       const int n0 = jr * NXn + (I - i0);
       const int ns[4] = {s0, s0, s1, s1};
-      const int nkk[4] = {k, k, k + 1, k + 1};
       const int ne[4] = {n0, n0 + NXn, n0 + NXn, n0};  // (I,j,k) (I,j+1,k) (I,j+1,k+1) (I,j,k+1)
+      const long long g0 = nb0 + (jr * E + (I - i0));
+      const long long go[4] = {g0, g0 + E, g0 + nplane + E, g0 + nplane};
       double S[3], F[4];
-      const long long p = pidx(B, I, jj, k);
+      const long long p = cell_at(I, jj, k);
 #pragma unroll
       for (int x = 0; x < 3; ++x) S[x] = met[ML::S(0, x) * vs + p];
-      face(s0, cr - 1, s0, cr, ns, ne, nkk, S, F);
+      face(s0, cr - 1, s0, cr, ns, ne, go, S, F);
 #pragma unroll
       for (int w = 0; w < 4; ++w) fx[w][e] = F[w];
     }
@@ -544,13 +553,14 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
       const int cr = (J - j0 + 1) * CX + ic + 1;
       const int n0 = (J - j0) * NXn + ic;
       const int ns[4] = {s0, s0, s1, s1};
-      const int nkk[4] = {k, k, k + 1, k + 1};
       const int ne[4] = {n0, n0 + 1, n0 + 1, n0};  // (i,J,k) (i+1,J,k) (i+1,J,k+1) (i,J,k+1)
+      const long long g0 = nb0 + ((J - j0) * E + ic);
+      const long long go[4] = {g0, g0 + 1, g0 + nplane + 1, g0 + nplane};
       double S[3], F[4];
-      const long long p = pidx(B, ii, J, k);
+      const long long p = cell_at(ii, J, k);
 #pragma unroll
       for (int x = 0; x < 3; ++x) S[x] = met[ML::S(1, x) * vs + p];
-      face(s0, cr - CX, s0, cr, ns, ne, nkk, S, F);
+      face(s0, cr - CX, s0, cr, ns, ne, go, S, F);
 #pragma unroll
       for (int w = 0; w < 4; ++w) fy[w][e] = F[w];
     }
@@ -558,7 +568,7 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     if (own) zface(k + 1, s0, s1, s1, fzhi);
     __syncthreads();
     if (own) {
-      const long long p = pidx(B, i, j, k);
+      const long long p = cell_at(i, j, k);
       const double iv = met[ML::INVVOL * vs + p];
       const long long cell = B.packed + ((long long)k * B.nj + j) * B.ni + i;
       const int ex = ty * NXn + tx, ey = ty * VT_X + tx;
