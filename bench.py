@@ -444,6 +444,7 @@ def main():
         out["ramp_2d"] = bench_ramp()
         print("[bench] laminar Navier-Stokes vs Euler on the same workload", file=sys.stderr, flush=True)
         out["navier_stokes"] = bench_navier_stokes(args.workload, args.n, out["config"]["tile_variant"])
+        out["navier_stokes_2d"] = bench_navier_stokes("compression_ramp", 1024, 2, steps=10, warmup=3)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

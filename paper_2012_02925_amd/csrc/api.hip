@@ -634,9 +634,9 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   if (c->freezing) c->off_phi = take((size_t)c->phi_doubles * 8);
   if (c->viscous) {
     c->vis_tiles.clear();
-    if (dim == 3) {
+    {
       int vx, vy, vk;
-      viscous_tile_shape(&vx, &vy, &vk);
+      viscous_tile_shape(dim, &vx, &vy, &vk);
       for (int b = 0; b < nb; ++b)
         for (int k0 = 0; k0 < c->blocks[b].nk; k0 += vk)
           for (int j0 = 0; j0 < c->blocks[b].nj; j0 += vy)

@@ -36,20 +36,20 @@ struct ViscArgs {
   double mu;               // viscosity
   double kcond;            // conductivity mu / ((gamma - 1) Pr)
   double gamma;
-  const TileDev* tiles;    // 3D: tiles of viscous_tile_shape over every block
+  const TileDev* tiles;    // tiles of viscous_tile_shape over every block (fused pass)
   int ntiles;
 };
 
-// Tile shape (cells along i, j and planes along k) of the fused 3D pass; the
+// Tile shape (cells along i, j and planes along k) of the fused pass; the
 // host lists tiles of this shape over every block.
-void viscous_tile_shape(int* tx, int* ty, int* tk);
+void viscous_tile_shape(int dim, int* tx, int* ty, int* tk);
 
 hipError_t launch_cell_centers(int dim, const ViscArgs& a, long long max_cells, int nblocks, hipStream_t s);
 hipError_t launch_ghost_centers(int dim, const ViscArgs& a, int nchunks, hipStream_t s);
 // mode 0: pseudo-node positions from the centres; 1: values from the state
 hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, int mode, long long max_nodes, int nblocks, hipStream_t s);
-// Per stage.  2D: temperatures, pseudo-node values, face fluxes (each face
-// once), divergence into rv.  3D: one fused tiled pass (same arithmetic).  max_padded bounds (ni+2)(nj+2)(nk+2), max_nodes the
+// Per stage: one fused tiled pass (2D or 3D; with no tile list the 2D
+// chain of temperatures, pseudo-node values, face fluxes and divergence).  max_padded bounds (ni+2)(nj+2)(nk+2), max_nodes the
 // node count of a block.
 hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_padded, long long max_nodes, long long max_cells,
                           int nblocks, hipStream_t s);

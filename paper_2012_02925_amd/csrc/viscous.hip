@@ -582,6 +582,158 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
   }
 }
 
+// Fused 2D pass over a VT2 x VT2 tile: cells with a one-cell halo ring
+// (centre, velocity, temperature) and the tile's pseudo-node values in LDS,
+// every face once (own low faces plus the tile's high edges), Rv per cell.
+// Same arithmetic as the per-face 2D kernels.
+constexpr int VT2 = 16;
+
+__global__ void __launch_bounds__(VT2* VT2) viscous_tile2d_kernel(ViscArgs a) {
+  using ML = MetricLayout<2>;
+  constexpr int NT = VT2 * VT2;
+  constexpr int CX = VT2 + 2, NC = CX * CX;
+  constexpr int NXn = VT2 + 1, NN = NXn * NXn;
+  constexpr int NFX = NXn * VT2, NFY = VT2 * NXn;
+  __shared__ double sc[5][NC];  // centre x, y, velocity u, v, temperature
+  __shared__ double sn[3][NN];  // pseudo-node u, v, T
+  __shared__ double fx[3][NFX];
+  __shared__ double fy[3][NFY];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % VT2, ty = tid / VT2;
+  const TileDev tile = a.tiles[blockIdx.x];
+  const BlockDev B = a.blocks[tile.block];
+  const int i0 = tile.i0, j0 = tile.j0;
+  const long long vs = B.vstride;
+  const double* met = a.metric + B.morigin;
+  const double* cen = a.centers + B.corigin;
+  const double* q = a.q + B.origin;
+  const int E = B.ni + 1;
+  const long long nb0 = node_index(B, i0, j0, 0);
+
+  for (int e = tid; e < NC; e += NT) {
+    const int ii = i0 - 1 + e % CX, jj = j0 - 1 + e / CX;
+    const int out = (ii < 0 || ii >= B.ni) + (jj < 0 || jj >= B.nj);
+    if (ii <= B.ni && jj <= B.nj && out <= 1) {
+      const long long p = jj * B.pi + ii;
+      sc[0][e] = cen[p];
+      sc[1][e] = cen[vs + p];
+      sc[2][e] = q[vs + p];
+      sc[3][e] = q[2 * vs + p];
+      sc[4][e] = a.gamma * q[3 * vs + p] / q[p];
+    } else {
+#pragma unroll
+      for (int w = 0; w < 5; ++w) sc[w][e] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NN; e += NT) {
+    const int I = i0 + e % NXn, J = j0 + e / NXn;
+    if (I > B.ni || J > B.nj) continue;
+    double acc[3] = {0.0, 0.0, 0.0};
+    int cnt = 0;
+#pragma unroll
+    for (int ai = 0; ai < 2; ++ai)
+#pragma unroll
+      for (int aj = 0; aj < 2; ++aj) {
+        const int out = (ai == 0 ? I == 0 : I == B.ni) + (aj == 0 ? J == 0 : J == B.nj);
+        if (out > 1) continue;
+        const int c = (J - j0 + aj) * CX + (I - i0 + ai);
+        ++cnt;
+#pragma unroll
+        for (int w = 0; w < 3; ++w) acc[w] += sc[2 + w][c];
+      }
+    const double rc = 1.0 / (double)cnt;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) sn[w][e] = acc[w] * rc;
+  }
+  __syncthreads();
+  // face between LDS cells cl and cr; pseudo-nodes n0, n1 (frame) / g0, g1 (global)
+  auto face = [&](int cl, int cr, int n0, int n1, long long g0, long long g1, const double* S, double* F) {
+    double D[2], VL[3], VR[3], P[2][2], W[2][3], G[3][2], uf[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) D[x] = sc[x][cr] - sc[x][cl];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      VL[w] = sc[2 + w][cl];
+      VR[w] = sc[2 + w][cr];
+      W[0][w] = sn[w][n0];
+      W[1][w] = sn[w][n1];
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      P[0][x] = a.npos[x * B.nnode_total + g0];
+      P[1][x] = a.npos[x * B.nnode_total + g1];
+    }
+    dual_gradient<2>(D, VL, VR, P, W, G);
+#pragma unroll
+    for (int x = 0; x < 2; ++x) uf[x] = 0.5 * (VL[x] + VR[x]);
+    viscous_flux<2>(G, uf, S, a.mu, a.kcond, F);
+  };
+  auto xface = [&](int I, int jj, double* F) {  // nodes (I, j), (I, j+1)
+    const int cr = (jj - j0 + 1) * CX + (I - i0 + 1);
+    const int n0 = (jj - j0) * NXn + (I - i0);
+    const long long g0 = nb0 + ((jj - j0) * E + (I - i0));
+    double S[2];
+    const long long p = jj * B.pi + I;
+    S[0] = met[ML::S(0, 0) * vs + p];
+    S[1] = met[ML::S(0, 1) * vs + p];
+    face(cr - 1, cr, n0, n0 + NXn, g0, g0 + E, S, F);
+  };
+  auto yface = [&](int ii, int J, double* F) {  // nodes (i, J), (i+1, J)
+    const int cr = (J - j0 + 1) * CX + (ii - i0 + 1);
+    const int n0 = (J - j0) * NXn + (ii - i0);
+    const long long g0 = nb0 + ((J - j0) * E + (ii - i0));
+    double S[2];
+    const long long p = J * B.pi + ii;
+    S[0] = met[ML::S(1, 0) * vs + p];
+    S[1] = met[ML::S(1, 1) * vs + p];
+    face(cr - CX, cr, n0, n0 + 1, g0, g0 + 1, S, F);
+  };
+  const int i = i0 + tx, j = j0 + ty;
+  if (i <= B.ni && j < B.nj) {
+    double F[3];
+    xface(i, j, F);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) fx[w][ty * NXn + tx] = F[w];
+  }
+  if (i < B.ni && j <= B.nj) {
+    double F[3];
+    yface(i, j, F);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) fy[w][ty * VT2 + tx] = F[w];
+  }
+  if (tid < VT2) {  // x-faces of the tile's high i-edge
+    const int I = i0 + VT2, jj = j0 + tid;
+    if (I <= B.ni && jj < B.nj) {
+      double F[3];
+      xface(I, jj, F);
+#pragma unroll
+      for (int w = 0; w < 3; ++w) fx[w][tid * NXn + VT2] = F[w];
+    }
+  } else if (tid < 2 * VT2) {  // y-faces of the tile's high j-edge
+    const int ii = i0 + tid - VT2, J = j0 + VT2;
+    if (ii < B.ni && J <= B.nj) {
+      double F[3];
+      yface(ii, J, F);
+#pragma unroll
+      for (int w = 0; w < 3; ++w) fy[w][VT2 * VT2 + tid - VT2] = F[w];
+    }
+  }
+  __syncthreads();
+  if (i < B.ni && j < B.nj) {
+    const long long p = j * B.pi + i;
+    const double iv = met[ML::INVVOL * vs + p];
+    const long long cell = B.packed + (long long)j * B.ni + i;
+    const int ex = ty * NXn + tx, ey = ty * VT2 + tx;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const double acc = (fx[w][ex + 1] - fx[w][ex]) + (fy[w][ey + VT2] - fy[w][ey]);
+      a.rv[w * B.ncell_total + cell] = acc * iv;
+    }
+  }
+}
+
 dim3 grid_of(long long items, int nblocks) { return dim3((unsigned)((items + 255) / 256), (unsigned)nblocks); }
 
 }  // namespace
@@ -611,15 +763,17 @@ hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, int mode, long long m
   return hipGetLastError();
 }
 
-void viscous_tile_shape(int* tx, int* ty, int* tk) {
-  *tx = VT_X;
-  *ty = VT_Y;
-  *tk = VT_K;
+void viscous_tile_shape(int dim, int* tx, int* ty, int* tk) {
+  *tx = dim == 2 ? VT2 : VT_X;
+  *ty = dim == 2 ? VT2 : VT_Y;
+  *tk = dim == 2 ? 1 : VT_K;
 }
 
 hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_padded, long long max_nodes, long long max_cells,
                           int nblocks, hipStream_t s) {
-  if (dim == 2) {
+  if (dim == 2 && a.ntiles > 0) {
+    hipLaunchKernelGGL(viscous_tile2d_kernel, dim3(a.ntiles), dim3(VT2 * VT2), 0, s, a);
+  } else if (dim == 2) {
     hipLaunchKernelGGL(temperature_kernel<2>, grid_of(max_padded, nblocks), dim3(256), 0, s, a);
     hipLaunchKernelGGL(pseudo_nodes_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a, 1);
     hipLaunchKernelGGL(viscous_faces_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a);
