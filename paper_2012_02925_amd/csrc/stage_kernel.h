@@ -25,6 +25,11 @@
 // Global latency is hidden by prefetching: the next plane's halo item and
 // q_k+3 are loaded while the current plane computes, and the own cell's
 // metrics and stage-start state are loaded before the plane's first barrier.
+// Those loads are issued by every lane, without a branch, from addresses kept
+// in bounds (lanes without a cell read a cell of the block): where a load is
+// issued under a condition, the compiler's wait counting cannot tell at the
+// join how many loads are still in flight and waits for all of them, so a
+// prefetch issued just before would be waited for at once.
 #pragma once
 
 #include "cfd_internal.h"
@@ -151,7 +156,9 @@ stage_kernel(StageArgs a) {
   constexpr int NXF = TY + TX;          // faces on the tile's high edges
   using ML = MetricLayout<DIM>;
   constexpr int NH = (NHALO + NT - 1) / NT;  // halo items per thread
+  constexpr int NWAVE = NT / 64;
   static_assert(NXS <= NT && NXF <= NT, "tile too flat for one halo slope per thread");
+  static_assert(NT % 64 == 0, "whole wavefronts per workgroup");
 
   __shared__ double sq[NV][LP];        // plane primitives with halo, [ly][lx]
   __shared__ double slx[NS][NV][NSX];  // i-slopes (+, -)
@@ -195,7 +202,12 @@ stage_kernel(StageArgs a) {
     const unsigned p8 = (unsigned)plane * 8u;
     const int kbeg = DIM == 3 ? tile.k0 : 0;
     const int kend = DIM == 3 ? min(tile.k0 + KC, B.nk) : 1;
-    const long long oc = pidx(B, i, j, 0) + K;  // own column, plane 0
+    // own column, plane 0; lanes beyond the padded block take the block's
+    // first column so every load below has an in-bounds address and can be
+    // issued without a branch (conditionally issued loads make the compiler
+    // wait for all outstanding loads, prefetches included, where the paths
+    // join)
+    const long long oc = (own_in_pad ? pidx(B, i, j, 0) : 0) + K;
     auto zoff = [&](int k) { return (unsigned)((oc + (long long)k * plane) * 8); };
 
     // this thread's halo-ring items (the same for every plane of the tile)
@@ -225,14 +237,31 @@ stage_kernel(StageArgs a) {
         }
       }
     }
+    // Lanes of rank rs < NXS take a halo cell's slope, lanes of rank re < NXF
+    // a face on the tile's high edges.  In 2D (one plane per tile) the ranks
+    // rotate over the waves from tile to tile, so this extra work does not
+    // always fall on the same SIMD of a compute unit; in 3D they are tid.
+    const int rot = DIM == 2 ? t % NWAVE : 0;
+    const int rs = DIM == 2 ? (tid + NT - 64 * ((rot + 1) % NWAVE)) % NT : tid;
+    const int re = DIM == 2 ? (tid + NT - 64 * rot) % NT : tid;
+    // this lane's face on the tile's high edges: i-face i0+TX of row re, then
+    // j-face j0+TY of column re-TY; plane-0 offset of its area vector (an
+    // in-bounds cell where the face lies outside the block)
+    int edge_d = 0;
+    unsigned edge_off = 0;
+    if (re < NXF) {
+      const int fi = re < TY ? i0 + TX : i0 + re - TY;
+      const int fj = re < TY ? j0 + re : j0 + TY;
+      edge_d = re < TY ? 0 : 1;
+      if (fi <= B.ni + 1 && fj <= B.nj + 1) edge_off = (unsigned)((pidx(B, fi, fj, 0) + K) * 8);
+    }
     double pre_h[NH][NV];  // prefetched halo values of the next plane
+    // unused items load the block's first cell (hoff = 0)
     auto fetch_halo = [&](int k) {
 #pragma unroll
       for (int h = 0; h < NH; ++h) {
-        if (hpos[h] >= 0) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) pre_h[h][v] = ld_at(qin + v * vs, hoff[h] + k * p8);
-        }
+        for (int v = 0; v < NV; ++v) pre_h[h][v] = ld_at(qin + v * vs, hoff[h] + k * p8);
       }
     };
 
@@ -286,7 +315,7 @@ stage_kernel(StageArgs a) {
       }
     };
     if constexpr (DIM == 3) {
-      if (own) {
+      {  // every lane (lanes without a cell work on an in-bounds column; results unused)
         double q2[NV], Sz[3];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -314,12 +343,18 @@ stage_kernel(StageArgs a) {
       const unsigned ok = zoff(k);  // own cell in plane k (byte offset)
       // own-cell metrics and stage-start state of this plane, consumed after
       // the slope phase
-      double Sx[DIM], Sy[DIM], Sz[DIM];
+      double Sx[DIM], Sy[DIM], Sz[DIM], Se[DIM];
 #pragma unroll
       for (int c = 0; c < DIM; ++c) {
-        if (fx_ok) Sx[c] = ld_at(met + ML::S(0, c) * vs, ok);
-        if (fy_ok) Sy[c] = ld_at(met + ML::S(1, c) * vs, ok);
-        if (DIM == 3 && own) Sz[c] = ld_at(met + ML::S(2, c) * vs, ok + p8);
+        Sx[c] = ld_at(met + ML::S(0, c) * vs, ok);
+        Sy[c] = ld_at(met + ML::S(1, c) * vs, ok);
+        if (DIM == 3) Sz[c] = ld_at(met + ML::S(2, c) * vs, ok + p8);
+      }
+      // area vector of this lane's face on the tile's high edge (issued
+      // before the halo prefetch, so waiting for it never waits for that)
+      if (re < NXF) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) Se[c] = ld_at(met + ML::S(edge_d, c) * vs, edge_off + k * p8);
       }
 
       // ---- 1. stage the plane with its halo in LDS ----------------------
@@ -339,7 +374,7 @@ stage_kernel(StageArgs a) {
       }
       __syncthreads();
       // prefetch the next plane's halo while this plane computes
-      if (DIM == 3 && k + 1 < kend) fetch_halo(k + 1);
+      if (DIM == 3) fetch_halo(k + 1 < kend ? k + 1 : k);
 
       // ---- 2. slopes: own cell (i and j), then the halo cells ------------
       {
@@ -348,8 +383,8 @@ stage_kernel(StageArgs a) {
           double sp, sm;
           if constexpr (LIM == LIM_FROZEN) {
             // cells beyond the padded block compute slopes nobody reads
-            const double fx = own_in_pad ? ld_at(phib + v * vs, ok) : 0.0;
-            const double fy = own_in_pad ? ld_at(phib + (NV + v) * vs, ok) : 0.0;
+            const double fx = ld_at(phib + v * vs, ok);
+            const double fy = ld_at(phib + (NV + v) * vs, ok);
             slx[0][v][ty * SXW + tx + 1] =
                 frozen_slope(fx, sq[v][own_lp] - sq[v][own_lp - 1], sq[v][own_lp + 1] - sq[v][own_lp]);
             sly[0][v][(ty + 1) * TX + tx] =
@@ -366,11 +401,11 @@ stage_kernel(StageArgs a) {
           if constexpr (NS == 2) sly[NS - 1][v][(ty + 1) * TX + tx] = sm;
         }
       }
-      if (tid < NXS) {
+      if (rs < NXS) {
         int p, st, dst, hi, hj;  // LDS cell, stride, slope slot, block cell
         bool isx;
-        if (tid < 2 * TY) {  // i-slopes of cells i0-1 and i0+TX
-          const int r = tid >> 1, side = tid & 1;
+        if (rs < 2 * TY) {  // i-slopes of cells i0-1 and i0+TX
+          const int r = rs >> 1, side = rs & 1;
           const int c = side ? TX + 1 : 0;
           p = (r + 2) * LX + c + 1;
           st = 1;
@@ -379,7 +414,7 @@ stage_kernel(StageArgs a) {
           hi = i0 - 1 + c;
           hj = j0 + r;
         } else {  // j-slopes of rows j0-1 and j0+TY
-          const int e = tid - 2 * TY;
+          const int e = rs - 2 * TY;
           const int c = e % TX, side = e / TX;
           const int r = side ? TY + 1 : 0;
           p = (r + 1) * LX + c + 2;
@@ -462,38 +497,34 @@ stage_kernel(StageArgs a) {
         for (int v = 0; v < NV; ++v) fly[v][ty * TX + tx] = F[v];
       }
       // faces on the tile's high edges: i-face i0+TX of each row, j-face j0+TY of each column
-      if (tid < NXF) {
-        int pL, st, sL, sR, fi, fj, d, dst;
+      if (re < NXF) {
+        int pL, st, sL, sR, fi, fj, dst;
         bool isx;
-        if (tid < TY) {
-          const int r = tid;
+        if (re < TY) {
+          const int r = re;
           pL = (r + 2) * LX + TX + 1;
           st = 1;
           sL = r * SXW + TX;
           sR = sL + 1;
           fi = i0 + TX;
           fj = j0 + r;
-          d = 0;
           dst = r * FXW + TX;
           isx = true;
         } else {
-          const int c = tid - TY;
+          const int c = re - TY;
           pL = (TY + 1) * LX + c + 2;
           st = LX;
           sL = TY * TX + c;
           sR = sL + TX;
           fi = i0 + c;
           fj = j0 + TY;
-          d = 1;
           dst = TY * TX + c;
           isx = false;
         }
         const bool valid = isx ? (fi <= B.ni && fj < B.nj) : (fi < B.ni && fj <= B.nj);
         if (valid) {
-          double S[DIM], F[NV];
-          const unsigned fidx = (unsigned)((pidx(B, fi, fj, k) + K) * 8);
-#pragma unroll
-          for (int c = 0; c < DIM; ++c) S[c] = ld_at(met + ML::S(d, c) * vs, fidx);
+          const double* S = Se;
+          double F[NV];
           const int face = isx ? (fi == B.ni ? 1 : -1) : (fj == B.nj ? 3 : -1);
           if (is_wall(a, B, tile.block, face, isx ? fj : fi, k)) {
             wall_flux<DIM>(wall_pressure(sq[NV - 1][pL], sq[NV - 1][pL - st]), S, F);
@@ -521,35 +552,33 @@ stage_kernel(StageArgs a) {
       }
       // inverse volume, stage-start state and (local stepping) the cell's time
       // step, consumed after the next barrier
-      double iv = 0.0, w0[NV], adtc = adt;
-      const long long pcell = B.packed + ((long long)k * B.nj + j) * B.ni + i;
-      if (own) {
-        iv = ld_at(met + ML::INVVOL * vs, ok);
-        if (update && a.dtloc) adtc = a.alpha * a.dtloc[pcell];
-        if (update && !q0_is_qin) {
-          const double* q0 = a.q0 + (B.origin - K);
+      // (every lane loads; lanes without a cell read an in-bounds cell)
+      double w0[NV], adtc = adt;
+      const long long pcell = B.packed + (own ? ((long long)k * B.nj + j) * B.ni + i : 0);
+      const double iv = ld_at(met + ML::INVVOL * vs, ok);
+      if (update && a.dtloc) adtc = a.alpha * a.dtloc[pcell];
+      if (update && !q0_is_qin) {
+        const double* q0 = a.q0 + (B.origin - K);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) w0[v] = ld_at(q0 + v * vs, ok);
-        }
+        for (int v = 0; v < NV; ++v) w0[v] = ld_at(q0 + v * vs, ok);
       }
       // k-face k+1 of the own column (queue: q(k) in LDS, q(k+1), q(k+2)), then
-      // the k part of the divergence; prefetch q(k+3) for the next plane
+      // the k part of the divergence; prefetch q(k+3) for the next plane (the
+      // current plane again after the tile's last plane).  Lanes without a
+      // cell compute on their in-bounds column and their results are unused.
       if constexpr (DIM == 3) {
-        if (own) {
-          double qcur[NV], fz[NV];
+        double qcur[NV], fz[NV];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) qcur[v] = sq[v][own_lp];
-          zstep(k, qcur, qnx, Sz, fz);
+        for (int v = 0; v < NV; ++v) qcur[v] = sq[v][own_lp];
+        zstep(k, qcur, qnx, Sz, fz);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            fzd[v] = fz[v] - fzs[v][tid];
-            fzs[v][tid] = fz[v];
-          }
-          if (k + 1 < kend) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) qnx[v] = ld_at(qin + v * vs, ok + 3 * p8);
-          }
+        for (int v = 0; v < NV; ++v) {
+          fzd[v] = fz[v] - fzs[v][tid];
+          fzs[v][tid] = fz[v];
         }
+        const unsigned o3 = ok + (k + 1 < kend ? 3u * p8 : 0u);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qnx[v] = ld_at(qin + v * vs, o3);
       }
       __syncthreads();
 
@@ -609,7 +638,9 @@ stage_kernel(StageArgs a) {
           }
         }
       }
-      __syncthreads();
+      // No barrier here: the next plane's staging writes sq, whose last
+      // reads by other threads (face states) precede the barrier above, and
+      // flx/fly, read just now, are written again only after two barriers.
     }
   }
 
