@@ -525,9 +525,6 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     __syncthreads();
     make_nodes(k + 1, s0, s1, s1);
     __syncthreads();
-    if (k + 1 < k1) {  // plane k+2 and node plane k+2 while this plane's faces compute
-      fetch_cells(k + 2);
-    }
     const long long nb0 = node_base(k);  // node (i0, j0, k)
     // x-faces (I, j) and y-faces (i, J) of plane k
     for (int e = tid; e < NFX; e += NT) {
@@ -566,6 +563,9 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     }
     double fzhi[4];
     if (own) zface(k + 1, s0, s1, s1, fzhi);
+    // plane k+2 while the divergence and the next plane's staging run (issued
+    // after the face loops' own loads, which would otherwise wait for it)
+    if (k + 1 < k1) fetch_cells(k + 2);
     __syncthreads();
     if (own) {
       const long long p = cell_at(i, j, k);
