@@ -137,7 +137,10 @@ constexpr int stage_waves() {
 
 // FF: the launch has farfield faces.  Kernels without them keep the farfield
 // test out of the face loops, whose register budget is tight in 3D.
-template <int DIM, int LIM, int TX, int TY, int KC, int FLUX, bool FF>
+// DT: the launch reduces Omega / lambda for the next time step (a.dtmin set,
+// the last stage of a step).  The other stages run an instantiation without
+// that epilogue, so its loads and registers do not weigh on them.
+template <int DIM, int LIM, int TX, int TY, int KC, int FLUX, bool FF, bool DT>
 __global__ void __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(stage_waves<DIM, LIM, TX, TY>())))
 stage_kernel(StageArgs a) {
   constexpr int NV = DIM + 2;
@@ -562,6 +565,11 @@ stage_kernel(StageArgs a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) w0[v] = ld_at(q0 + v * vs, ok);
       }
+      double rvc[NV - 1];  // viscous residual of the cell (Navier-Stokes)
+      if (a.rv) {
+#pragma unroll
+        for (int v = 1; v < NV; ++v) rvc[v - 1] = a.rv[(v - 1) * B.ncell_total + pcell];
+      }
       // k-face k+1 of the own column (queue: q(k) in LDS, q(k+1), q(k+2)), then
       // the k part of the divergence; prefetch q(k+3) for the next plane (the
       // current plane again after the tile's last plane).  Lanes without a
@@ -583,6 +591,21 @@ stage_kernel(StageArgs a) {
       __syncthreads();
 
       // ---- 4. divergence and update ---------------------------------------
+      // (DT) mean area vectors Sbar_d of the cell, all loads issued at once
+      // ahead of the divergence (issued one pair at a time, their latency
+      // was exposed in turn)
+      double sbar[DT ? DIM : 1][DIM];
+      if constexpr (DT) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const unsigned step = d == 0 ? 8u : (d == 1 ? 8u * B.pi : p8);
+#pragma unroll
+          for (int cc = 0; cc < DIM; ++cc) {
+            const double* md = met + ML::S(d, cc) * vs;
+            sbar[d][cc] = 0.5 * (ld_at(md, ok) + ld_at(md, ok + step));
+          }
+        }
+      }
       if (own) {
         const int ex = ty * FXW + tx;
         const int ey = ty * TX + tx;
@@ -595,7 +618,7 @@ stage_kernel(StageArgs a) {
         }
         if (a.rv) {
 #pragma unroll
-          for (int v = 1; v < NV; ++v) R[v] -= a.rv[(v - 1) * B.ncell_total + pcell];
+          for (int v = 1; v < NV; ++v) R[v] -= rvc[v - 1];
         }
         if (!update) {
 #pragma unroll
@@ -613,18 +636,16 @@ stage_kernel(StageArgs a) {
           double* qo = a.qout + (B.origin - K);
 #pragma unroll
           for (int v = 0; v < NV; ++v) st_at(qo + v * vs, ok, qnew[v]);
-          if (a.dtmin) {
+          if constexpr (DT) {
             // Omega / lambda with lambda = sum_d |u . Sbar_d| + c |Sbar_d|
             const double c = sqrt(a.gas.gamma * qnew[NV - 1] / qnew[0]);
             double lam = 0.0, s2sum = 0.0;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-              const unsigned step = d == 0 ? 8u : (d == 1 ? 8u * B.pi : p8);
               double un = 0.0, s2 = 0.0;
 #pragma unroll
               for (int cc = 0; cc < DIM; ++cc) {
-                const double* md = met + ML::S(d, cc) * vs;
-                const double sb = 0.5 * (ld_at(md, ok) + ld_at(md, ok + step));
+                const double sb = sbar[d][cc];
                 un += qnew[1 + cc] * sb;
                 s2 += sb * sb;
               }
@@ -644,7 +665,7 @@ stage_kernel(StageArgs a) {
     }
   }
 
-  if (a.dtmin) {
+  if constexpr (DT) {
     // workgroup minimum -> one atomic per workgroup
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) my_min = fmin(my_min, __shfl_xor(my_min, off));

@@ -13,10 +13,18 @@ namespace cfd {
 template <int DIM, int LIM, int TX, int TY, int KC, int FLUX>
 inline hipError_t launch_stage_t(bool ff, const StageArgs& a, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (ff)
-    hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC, FLUX, true>), dim3(grid), dim3(TX * TY), 0, s, a);
-  else
-    hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC, FLUX, false>), dim3(grid), dim3(TX * TY), 0, s, a);
+  const dim3 g(grid), b(TX * TY);
+  if (ff) {
+    if (a.dtmin)
+      hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC, FLUX, true, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC, FLUX, true, false>), g, b, 0, s, a);
+  } else {
+    if (a.dtmin)
+      hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC, FLUX, false, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((stage_kernel<DIM, LIM, TX, TY, KC, FLUX, false, false>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 
