@@ -67,9 +67,10 @@ __device__ __forceinline__ double slope(double a, double b, double e2) {
     double num = a * ab + aa * b;
     return den > SLOPE_TINY ? num * rcp(den) : 0.0;
   } else {
-    double a2 = a * a, b2 = b * b;
-    double den = a2 + b2 + 2.0 * e2;
-    double num = (b2 + e2) * a + (a2 + e2) * b;
+    // with A = a^2 + e^2, B = b^2 + e^2: S = (B a + A b) / (A + B)
+    const double A = fma(a, a, e2), B = fma(b, b, e2);
+    const double den = A + B;
+    const double num = fma(B, a, A * b);
     return den > SLOPE_TINY ? num * rcp(den) : 0.0;
   }
 }

@@ -638,7 +638,10 @@ stage_kernel(StageArgs a) {
           for (int v = 0; v < NV; ++v) st_at(qo + v * vs, ok, qnew[v]);
           if constexpr (DT) {
             // Omega / lambda with lambda = sum_d |u . Sbar_d| + c |Sbar_d|
-            const double c = sqrt(a.gas.gamma * qnew[NV - 1] / qnew[0]);
+            // (reciprocal and square roots from the hardware estimates with a
+            // Newton step: the step needs no correct rounding)
+            const double c2 = a.gas.gamma * qnew[NV - 1] * rcp(qnew[0]);
+            const double c = c2 * rsq(c2);
             double lam = 0.0, s2sum = 0.0;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
@@ -649,11 +652,11 @@ stage_kernel(StageArgs a) {
                 un += qnew[1 + cc] * sb;
                 s2 += sb * sb;
               }
-              lam += fabs(un) + c * sqrt(s2);
+              lam += fabs(un) + c * (s2 > 0.0 ? s2 * rsq(s2) : 0.0);
               s2sum += s2;
             }
             if (a.visc_cv > 0.0) lam += a.visc_cv / qnew[0] * s2sum * iv;
-            const double om = 1.0 / (lam * iv);
+            const double om = rcp(lam * iv);
             my_min = fmin(my_min, om);
             if (a.dtloc) a.dtloc[pcell] = a.cfl * om;
           }
