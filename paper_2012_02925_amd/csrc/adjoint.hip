@@ -351,6 +351,11 @@ __global__ void __launch_bounds__(TX* TY) vjp_tile2d_kernel(VjpArgs a) {
   double* fyCR = fyCL + NFY;
 
   const int tid = threadIdx.x;
+  // rank of this lane in the face and cell-item rounds: the last, partial
+  // round of each falls on a few waves, which rotate from tile to tile so the
+  // extra work does not always land on the same SIMD
+  static_assert(NT % 64 == 0, "whole wavefronts per workgroup");
+  const int rt = (tid + 64 * (int)(blockIdx.x % (NT / 64))) % NT;
   const TileDev tile = a.vtiles[blockIdx.x];
   const int b = tile.block;
   const BlockDev B = a.blocks[b];
@@ -373,7 +378,7 @@ __global__ void __launch_bounds__(TX* TY) vjp_tile2d_kernel(VjpArgs a) {
   __syncthreads();
 
   // ---- faces
-  for (int e = tid; e < NFX + NFY; e += NT) {
+  for (int e = rt; e < NFX + NFY; e += NT) {
     const int d = e < NFX ? 0 : 1;
     int f, t, slot, lc, st;
     if (d == 0) {
@@ -487,7 +492,7 @@ __global__ void __launch_bounds__(TX* TY) vjp_tile2d_kernel(VjpArgs a) {
   for (int v = 0; v < NV; ++v) qown[v] = sq[v][(tid / TX + 3) * LX + tid % TX + 3];
 #pragma unroll
   for (int it = 0; it < RPT; ++it) {
-    const int e = tid + it * NT;
+    const int e = rt + it * NT;
 #pragma unroll
     for (int v = 0; v < NV; ++v) rOwn[it][v] = rG[it][v] = rH[it][v] = 0.0;
     rI[it] = 0.0;
@@ -552,7 +557,7 @@ __global__ void __launch_bounds__(TX* TY) vjp_tile2d_kernel(VjpArgs a) {
   double* cI = cH + NV * NCI;          // [NCI]
 #pragma unroll
   for (int it = 0; it < RPT; ++it) {
-    const int e = tid + it * NT;
+    const int e = rt + it * NT;
     if (e >= NCI) continue;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {

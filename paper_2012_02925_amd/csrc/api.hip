@@ -707,6 +707,9 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
       for (int b = 0; b < nb; ++b)
         for (int j0 = 0; j0 < c->blocks[b].nj; j0 += VJP_TILE)
           for (int i0 = 0; i0 < c->blocks[b].ni; i0 += VJP_TILE) c->vtiles.push_back(TileDev{b, i0, j0, 0});
+    // XCD-aware order (each tile writes only its own outputs, so the order
+    // changes no result)
+    if (!c->vtiles.empty()) c->vtiles = xcd_order(c->vtiles, 0, c->vtiles.size());
     c->obj_chunks.clear();
     c->obj_begin.assign(nf + 1, 0);
     for (int f = 0; f < nf; ++f) {
