@@ -526,40 +526,50 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     make_nodes(k + 1, s0, s1, s1);
     __syncthreads();
     const long long nb0 = node_base(k);  // node (i0, j0, k)
-    // x-faces (I, j) and y-faces (i, J) of plane k
-    for (int e = tid; e < NFX; e += NT) {
-      const int I = i0 + e % NXn, jr = e / NXn, jj = j0 + jr;
-      if (I > B.ni || jj >= B.nj) continue;
-      const int cr = (jr + 1) * CX + (I - i0 + 1);
-      const int n0 = jr * NXn + (I - i0);
+    // x-faces (I, j) (flat index e = jr * NXn + I - i0) and y-faces (i, J)
+    // (e = (J - j0) * VT_X + i - i0) of plane k
+    auto xy_face = [&](bool isx, int e) {
+      int I, J;
+      if (isx) {
+        I = i0 + e % NXn;
+        J = j0 + e / NXn;
+        if (I > B.ni || J >= B.nj) return;
+      } else {
+        I = i0 + e % VT_X;
+        J = j0 + e / VT_X;
+        if (I >= B.ni || J > B.nj) return;
+      }
+      const int cr = (J - j0 + 1) * CX + (I - i0 + 1);
+      const int n0 = (J - j0) * NXn + (I - i0);
       const int ns[4] = {s0, s0, s1, s1};
-      const int ne[4] = {n0, n0 + NXn, n0 + NXn, n0};  // (I,j,k) (I,j+1,k) (I,j+1,k+1) (I,j,k+1)
-      const long long g0 = nb0 + (jr * E + (I - i0));
-      const long long go[4] = {g0, g0 + E, g0 + nplane + E, g0 + nplane};
+      // x: (I,j,k) (I,j+1,k) (I,j+1,k+1) (I,j,k+1); y: (i,J,k) (i+1,J,k) (i+1,J,k+1) (i,J,k+1)
+      const int n1 = isx ? n0 + NXn : n0 + 1;
+      const int ne[4] = {n0, n1, n1, n0};
+      const long long g0 = nb0 + ((J - j0) * E + (I - i0));
+      const long long g1 = isx ? g0 + E : g0 + 1;
+      const long long go[4] = {g0, g1, g1 + nplane, g0 + nplane};
       double S[3], F[4];
-      const long long p = cell_at(I, jj, k);
+      const long long p = cell_at(I, J, k);
 #pragma unroll
-      for (int x = 0; x < 3; ++x) S[x] = met[ML::S(0, x) * vs + p];
-      face(s0, cr - 1, s0, cr, ns, ne, go, S, F);
+      for (int x = 0; x < 3; ++x) S[x] = met[ML::S(isx ? 0 : 1, x) * vs + p];
+      face(s0, isx ? cr - 1 : cr - CX, s0, cr, ns, ne, go, S, F);
 #pragma unroll
-      for (int w = 0; w < 4; ++w) fx[w][e] = F[w];
-    }
-    for (int e = tid; e < NFY; e += NT) {
-      const int ic = e % VT_X, J = j0 + e / VT_X, ii = i0 + ic;
-      if (ii >= B.ni || J > B.nj) continue;
-      const int cr = (J - j0 + 1) * CX + ic + 1;
-      const int n0 = (J - j0) * NXn + ic;
-      const int ns[4] = {s0, s0, s1, s1};
-      const int ne[4] = {n0, n0 + 1, n0 + 1, n0};  // (i,J,k) (i+1,J,k) (i+1,J,k+1) (i,J,k+1)
-      const long long g0 = nb0 + ((J - j0) * E + ic);
-      const long long go[4] = {g0, g0 + 1, g0 + nplane + 1, g0 + nplane};
-      double S[3], F[4];
-      const long long p = cell_at(ii, J, k);
-#pragma unroll
-      for (int x = 0; x < 3; ++x) S[x] = met[ML::S(1, x) * vs + p];
-      face(s0, cr - CX, s0, cr, ns, ne, go, S, F);
-#pragma unroll
-      for (int w = 0; w < 4; ++w) fy[w][e] = F[w];
+      for (int w = 0; w < 4; ++w) {
+        if (isx)
+          fx[w][e] = F[w];
+        else
+          fy[w][e] = F[w];
+      }
+    };
+    // first NT of each kind, then the remaining NFX - NT x-faces and NFY - NT
+    // y-faces in one shared round (on one wave instead of two rounds)
+    static_assert(NFX - NT + NFY - NT <= 64, "leftover faces fit one wavefront");
+    // (a loop kept rolled: one face's arithmetic at a time in registers)
+#pragma unroll 1
+    for (int r = 0; r < 2; ++r) xy_face(r == 0, tid);
+    if (tid < NFX - NT + NFY - NT) {
+      const bool isx = tid < NFX - NT;
+      xy_face(isx, NT + (isx ? tid : tid - (NFX - NT)));
     }
     double fzhi[4];
     if (own) zface(k + 1, s0, s1, s1, fzhi);
