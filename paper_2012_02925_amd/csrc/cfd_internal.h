@@ -49,7 +49,7 @@ struct MetricLayout {
 
 // One direction of a connection: the donor's first two interior layers at
 // its face range fill the receiver's two ghost layers at its range.
-// Exchange-buffer segment layout: [var][layer][t2][t1] (layer 0 = adjacent).
+// Exchange-buffer segment layout: [var][t2][t1][layer] (layer 0 = adjacent).
 struct TransferDev {
   int rblock, rface, dblock, dface;
   int rlo0, rlo1, len0, len1;      // receiver range (len1 = 1 in 2D)

@@ -110,8 +110,10 @@ __global__ void __launch_bounds__(CHUNK) ghost_kernel(GhostArgs a) {
     const TransferDev x = a.xfers[ch.item];
     const int per_layer = x.len0 * x.len1;
     const int cnt = 2 * per_layer;
-    const int layer = e / per_layer;
-    const int r = e - layer * per_layer;
+    // the two layers of one face position are neighbouring elements (on an
+    // i-face the two cells share a cache line, so they go to adjacent lanes)
+    const int layer = e & 1;
+    const int r = e >> 1;
     const int r1 = r % x.len0, r2 = r / x.len0;
     double* seg = a.buf + x.buf;
     if (ch.kind == 0) {
@@ -135,9 +137,8 @@ __global__ void __launch_bounds__(CHUNK) ghost_kernel(GhostArgs a) {
   }
   // physical patch
   const PatchDev p = a.patches[ch.item];
-  const int per_layer = p.len0 * p.len1;
-  const int layer = e / per_layer;
-  const int r = e - layer * per_layer;
+  const int layer = e & 1;  // (layers of one face position side by side, as above)
+  const int r = e >> 1;
   const int t1 = p.lo0 + r % p.len0, t2 = p.lo1 + r / p.len0;
   const BlockDev& B = a.blocks[p.block];
   const long long vs = B.vstride;
