@@ -330,7 +330,7 @@ def main():
                     help="run only a plain device copy of 1 GiB (torch copy kernel) to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs the whole workload on one GPU; --gpus %d is not supported "
+        print("bench.py: cfdhip runs the whole workload on one GPU; --gpus %d is not supported "
               "(multi-GPU sharding is described in the design notes only)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -56,7 +56,7 @@ typedef enum {
   CFD_ERR_GRID = -4,        /* non-positive cell volume or degenerate face */
   CFD_ERR_HIP = -5,         /* HIP runtime error */
   CFD_ERR_NONFINITE = -6,   /* non-finite or non-physical state detected */
-  CFD_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+  CFD_ERR_UNSUPPORTED = -7  /* valid request the library does not implement */
 } cfd_status;
 
 enum { CFD_LIM_NONE = 0, CFD_LIM_VANLEER = 1, CFD_LIM_VANALBADA = 2 };
