@@ -102,6 +102,22 @@ def test_box3d_reduced_residual_and_steps():
     assert ok, rep
 
 
+@pytest.mark.parametrize("dims", [(2, 9, 2), (3, 2, 5), (37, 3, 2), (2, 2, 2), (2, 37, 1), (45, 3, 1)])
+def test_thin_blocks_residual_and_steps(dims):
+    """Blocks two or three cells thin: most lanes of a tile lie outside the
+    padded block, where the stage kernel's loads take clamped in-bounds
+    addresses and the results are discarded; every tile variant's residual and
+    four RK steps against the oracle."""
+    _say("case: thin periodic block", dims)
+    case = (synth.gaussian_bump_periodic(dims[0], dims[1], seed=13) if dims[2] == 1
+            else synth.jittered_periodic_box(dims=dims, seed=12))
+    s = check_residual(case)
+    Qref, dts = oracle_run(case, 4)
+    s.rk_step(4)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    assert ok, rep
+
+
 FVS = ["vanleer_fvs", "steger_warming"]
 
 
