@@ -98,6 +98,27 @@ def test_residual_vjp_matches_oracle_multiblock():
         _close(Xb[c], Xr[c], VJP_TOL, "Xbar[%d]" % c)
 
 
+@pytest.mark.parametrize("ni,nj", [(2, 17), (17, 2), (3, 33)])
+def test_residual_vjp_thin_periodic_blocks(ni, nj):
+    """Residual VJP on periodic blocks two or three cells thin (a block of 17
+    or 33 cells also leaves its last cell alone in a 16-wide tile, so those
+    cells go through the boundary pass): Q-bar and node cotangents against the
+    oracle's autograd."""
+    _say("case: thin periodic block %dx%d residual VJP" % (ni, nj))
+    case = synth.jittered_periodic_square(ni, nj, seed=16, limiter="vanalbada")
+    case.scheme.lim_eps = [1e-2, 1e-2, 1e-2, 1e-2 / 1.4]
+    s = _solver(case)
+    s.set_state(_conservative_from_prims(case).to("cuda:0"))
+    rng = np.random.default_rng(3)
+    Rbar = torch.tensor(rng.standard_normal((case.nvar, case.ncells)))
+    Qb, Xb, _ = s.residual_vjp(Rbar.to("cuda:0"), nodes=True)
+    Qr, Xr, _ = _oracle_vjp(case, Rbar)
+    for v in range(case.nvar):
+        _close(Qb[v], Qr[v], VJP_TOL, "Qbar[%d]" % v)
+    for c in range(2):
+        _close(Xb[c], Xr[c], VJP_TOL, "Xbar[%d]" % c)
+
+
 def test_residual_vjp_reversed_connection():
     _say("case: reversed 2-block connection residual VJP")
     base = synth.jittered_periodic_square(20, 14, seed=8, limiter="vanleer")

@@ -446,6 +446,24 @@ def test_navier_stokes_residual_and_steps(name):
     assert ok, rep
 
 
+@pytest.mark.parametrize("dims", [(2, 9, 3), (3, 2, 2), (2, 17, 1), (17, 3, 1)])
+def test_navier_stokes_thin_blocks(dims):
+    """Laminar Navier-Stokes on periodic blocks two or three cells thin: the
+    viscous pass's tiles are mostly outside the block and its pseudo-nodes
+    average cells across the periodic seam on both sides; residual and four
+    RK steps against the oracle."""
+    _say("case: NS thin periodic block", dims)
+    base = (synth.jittered_periodic_square(dims[0], dims[1], seed=15) if dims[2] == 1
+            else synth.jittered_periodic_box(dims=dims, seed=14))
+    case = _viscous(base, 0.01)
+    s = check_residual(case)
+    Qref, dts = oracle_run(case, 4)
+    s.rk_step(4)
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    _say("  after 4 steps", rep)
+    assert ok, rep
+
+
 @pytest.mark.parametrize("which", ["periodic_box", "char_box_noslip"])
 def test_navier_stokes_3d(which):
     _say("case: NS 3D", which)
