@@ -22,7 +22,7 @@ also defined when b = 0 (the ratio is never formed):
 
 (van Albada with the usual regularisation e, per primitive variable.)
 
-Limiter freezing (Sec. 6, the laminar airfoil case: the limiter is frozen
+Limiter freezing (Sec. 8.2, the laminar NACA 0012 case: the limiter is frozen
 late in a steady run so the residual keeps falling instead of oscillating; no
 formula is printed).  Reading: for the symmetric limiters S(a, b) = S(b, a),
 so one value per cell, direction and variable describes the limiter there,
