@@ -101,7 +101,24 @@ typedef struct {
   double viscosity;     /* laminar Navier-Stokes when > 0: constant viscosity in these units
                            (rho_inf = c_inf = 1), mu = M_inf / Re per unit length; 0 = Euler */
   double prandtl;       /* Prandtl number (0.72) when viscosity > 0 */
+  int debug_flags;      /* CFD_CHECK_FINITE | CFD_NAN_GHOSTS (0 for production runs) */
 } cfd_config;
+
+/* Debug checks (cfd_config.debug_flags; any other bit is CFD_ERR_ARG at
+ * cfd_create).  With any flag set, cfd_rk_step does not use its captured graph.
+ *   CFD_CHECK_FINITE  after every Runge-Kutta stage of cfd_rk_step the new
+ *                     state is checked on the device (density and pressure
+ *                     positive and finite, velocity finite); cfd_rk_step then
+ *                     synchronises after every step and returns
+ *                     CFD_ERR_NONFINITE, naming the step, if a stage failed
+ *                     (the state is left as that step produced it).
+ *                     cfd_residual checks its output for non-finite entries
+ *                     the same way.
+ *   CFD_NAN_GHOSTS    every ghost fill first writes quiet NaN into the whole
+ *                     ghost region of the state buffer (both layers, edges
+ *                     and corners), so a ghost value that the connections and
+ *                     patches do not provide shows up as NaN in the result. */
+enum { CFD_CHECK_FINITE = 1, CFD_NAN_GHOSTS = 2 };
 
 /* Version string of the library build. */
 const char* cfd_version(void);
@@ -207,7 +224,7 @@ cfd_status cfd_residual(cfd_ctx* ctx, double* dev_R);
  * partition of the cells and fixed reduction order. */
 cfd_status cfd_residual_norms(cfd_ctx* ctx, double* dev_R, double* dev_norms);
 
-/* Limiter freezing for steady runs (Sec. 6: the limiter is frozen late in a
+/* Limiter freezing for steady runs (Sec. 8.2, the laminar NACA 0012 case: the limiter is frozen late in a
  * steady run so the residual keeps falling; no formula is printed).  Reading:
  * per cell, direction and primitive variable the factor
  *   phi = S(a, b) / ((a + b)/2)   (0 where a + b = 0),
@@ -324,6 +341,22 @@ enum {
 };
 /* Integer facts about a finalized context. */
 cfd_status cfd_query(cfd_ctx* ctx, int what, long long* value);
+
+/* ---- measurement ------------------------------------------------------
+ * Streaming-bandwidth probe (no method arithmetic; a ceiling for the stage
+ * kernel's HBM rate): a kernel that reads element e of `reads` arrays and
+ * writes element e of `writes` arrays for e < n, each array n doubles
+ * (dev_src holds reads * n doubles, dev_dst writes * n, caller-owned device
+ * memory on the stream's device), with one double per lane per array
+ * (vec = 1, the stage kernel's 8-byte coalesced accesses) or two (vec = 2,
+ * 16-byte accesses; n even).  Supported (reads, writes): (1, 1), (3, 1),
+ * (4, 1), (15, 5), (20, 5) -- 20 reads and 5 writes per element is the
+ * stage kernel's per-cell traffic in 3D after the first stage.  One warm-up
+ * launch, then reps timed launches on hip_stream (hipStream_t, NULL = default);
+ * *ms_out = mean milliseconds per launch.  Synchronises.  Errors: CFD_ERR_ARG
+ * (null pointer, n <= 0, reps <= 0, vec, unsupported pair), CFD_ERR_HIP. */
+cfd_status cfd_stream_probe(int reads, int writes, int vec, const double* dev_src, double* dev_dst, long long n,
+                            int reps, void* hip_stream, double* ms_out);
 
 #ifdef __cplusplus
 }

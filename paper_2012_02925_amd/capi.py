@@ -18,6 +18,7 @@ BC = {"slip_wall": 1, "sup_inflow": 2, "extrap_outflow": 3, "farfield": 4, "sub_
       "noslip_wall": 7}
 DT_CFL, DT_FIXED, DT_LOCAL = 0, 1, 2
 EXEC_BATCHED, EXEC_PER_BLOCK = 0, 1
+CHECK_FINITE, NAN_GHOSTS = 1, 2  # cfd_config.debug_flags
 Q = {"nblocks": 0, "ncells": 1, "nvar": 2, "nvariants": 3, "variant": 4, "ntiles": 5, "ntransfers": 6,
      "npatches": 7, "nnodes": 8, "exchange_doubles": 9, "workspace_bytes": 10, "tile_x": 11, "tile_y": 12}
 
@@ -27,7 +28,8 @@ class CfdConfig(ctypes.Structure):
                 ("muscl_eps", ctypes.c_double), ("muscl_kappa", ctypes.c_double),
                 ("lim_eps", ctypes.c_double * 5), ("efix", ctypes.c_double), ("rk_stages", ctypes.c_int),
                 ("dt_mode", ctypes.c_int), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
-                ("flux", ctypes.c_int), ("viscosity", ctypes.c_double), ("prandtl", ctypes.c_double)]
+                ("flux", ctypes.c_int), ("viscosity", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("debug_flags", ctypes.c_int)]
 
 
 class CfdError(RuntimeError):
@@ -77,6 +79,7 @@ SIGNATURES = {
     "cfd_enable_limiter_freezing": ([_P, _I], _I),
     "cfd_freeze_limiter": ([_P, _I], _I),
     "cfd_rk_step_record": ([_P, _P], _I),
+    "cfd_stream_probe": ([_I, _I, _I, _P, _P, ctypes.c_longlong, _I, _P, _DP], _I),
     "cfd_rk_step_vjp_recorded": ([_P, _P, _P], _I),
     "cfd_objective_wall_pressure": ([_P, _P, _P], _I),
     "cfd_adjoint_result": ([_P, _P, _P], _I),

@@ -112,7 +112,7 @@ struct cfd_ctx {
   size_t off_dtloc = 0, off_normpart = 0;
   bool viscous = false;   // laminar Navier-Stokes (cfg.viscosity > 0)
   long long center_doubles = 0;
-  size_t off_centers = 0, off_npos = 0, off_nval = 0, off_rv = 0, off_vistiles = 0;
+  size_t off_centers = 0, off_npos = 0, off_rv = 0, off_vistiles = 0;
   std::vector<TileDev> vis_tiles;  // tiles of the fused 3D viscous pass
   bool freezing = false;  // workspace holds frozen-limiter arrays (cfd_enable_limiter_freezing)
   bool frozen = false;    // stage kernels use the frozen factors
@@ -241,6 +241,7 @@ extern "C" cfd_status cfd_create(const cfd_config* cfg, void* stream, cfd_ctx** 
     if (!(cfg->lim_eps[v] >= 0.0)) return CFD_ERR_ARG;
   if (!(cfg->viscosity >= 0.0) || !std::isfinite(cfg->viscosity)) return CFD_ERR_ARG;
   if (cfg->viscosity > 0.0 && !(cfg->prandtl > 0.0)) return CFD_ERR_ARG;
+  if (cfg->debug_flags & ~(CFD_CHECK_FINITE | CFD_NAN_GHOSTS)) return CFD_ERR_ARG;
   cfd_ctx* c = new cfd_ctx();
   c->cfg = *cfg;
   c->viscous = cfg->viscosity > 0.0;
@@ -475,9 +476,9 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     fcursor = align_ll(fcursor + 14 + (nfb - 1) * B.vstride + padded, 16);
     B.corigin = 0;
     if (c->viscous) {
-      // centre coordinates, temperature, dim x (dim+1) viscous face fluxes
+      // cell-centre coordinates
       B.corigin = ccursor + 14 + K;
-      ccursor = align_ll(ccursor + 14 + ((dim + 1) * (dim + 1) - 1) * B.vstride + padded, 16);
+      ccursor = align_ll(ccursor + 14 + (dim - 1) * B.vstride + padded, 16);
     }
     B.lorigin = 0;
     if (c->freezing) {
@@ -647,7 +648,6 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     c->off_vistiles = take(std::max<size_t>(c->vis_tiles.size(), 1) * sizeof(TileDev));
     c->off_centers = take((size_t)c->center_doubles * 8);
     c->off_npos = take((size_t)c->nnodes * dim * 8);
-    c->off_nval = take((size_t)c->nnodes * (dim + 1) * 8);
     c->off_rv = take((size_t)c->ncells * (dim + 1) * 8);
   }
   c->off_blocks = take(c->blocks.size() * sizeof(BlockDev));
@@ -766,7 +766,6 @@ static ViscArgs visc_args(cfd_ctx* c, const double* q) {
   v.metric = c->metric();
   v.centers = c->dptr<double>(c->off_centers);
   v.npos = c->dptr<double>(c->off_npos);
-  v.nval = c->dptr<double>(c->off_nval);
   v.q = q;
   v.rv = c->dptr<double>(c->off_rv);
   v.mu = c->cfg.viscosity;
@@ -797,7 +796,7 @@ static cfd_status recompute_metrics(cfd_ctx* c) {
     const int nb = (int)c->blocks.size();
     HIP_TRY(c, launch_cell_centers(c->dim, v, c->max_cells, nb, c->stream));
     HIP_TRY(c, launch_ghost_centers(c->dim, v, (int)c->chunks1.size(), c->stream));
-    HIP_TRY(c, launch_pseudo_nodes(c->dim, v, 0, c->max_nodes, nb, c->stream));
+    HIP_TRY(c, launch_pseudo_nodes(c->dim, v, c->max_nodes, nb, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   return CFD_OK;
@@ -944,8 +943,7 @@ static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s) {
   cfd_status st = fill_ghosts(c, q, s);
   if (st != CFD_OK || !c->viscous) return st;
   ViscArgs v = visc_args(c, q);
-  const int nb = (int)c->blocks.size();
-  HIP_TRY(c, launch_viscous(c->dim, v, c->max_padded, c->max_nodes, c->max_cells, nb, s));
+  HIP_TRY(c, launch_viscous(c->dim, v, s));
   return CFD_OK;
 }
 
@@ -953,6 +951,11 @@ static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s) {
 static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s) {
   GhostArgs g = ghost_args(c, q);
   const int nb = (int)c->blocks.size();
+  if (c->cfg.debug_flags & CFD_NAN_GHOSTS) {
+    CellArgs n = cell_args(c);
+    n.dst = q;
+    HIP_TRY(c, launch_nan_ghosts(c->dim, n, c->max_padded, nb, s));
+  }
   if (c->exec_mode == CFD_EXEC_PER_BLOCK) {
     g.chunks = c->dptr<ChunkDev>(c->off_chunks1);
     for (int b = 0; b < nb; ++b) {
@@ -1036,8 +1039,26 @@ static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
     a.dtmin = (k == M && cfl) ? c->dptr<unsigned long long>(c->off_dtmin) : nullptr;
     st = launch_stage_all(c, a, s, timed);
     if (st != CFD_OK) return st;
+    if (c->cfg.debug_flags & CFD_CHECK_FINITE) {
+      CellArgs ca = cell_args(c);
+      ca.src = out;
+      HIP_TRY(c, launch_check_state(c->dim, ca, c->max_cells, (int)c->blocks.size(), s));
+    }
     in = out;
   }
+  return CFD_OK;
+}
+
+// CFD_CHECK_FINITE: clear the device error flag / read it back (synchronises).
+static cfd_status debug_clear(cfd_ctx* c) {
+  HIP_TRY(c, hipMemsetAsync(c->dptr<int>(c->off_err), 0, sizeof(int), c->stream));
+  return CFD_OK;
+}
+static cfd_status debug_flagged(cfd_ctx* c, bool* bad) {
+  int err = 0;
+  HIP_TRY(c, hipMemcpyAsync(&err, c->dptr<int>(c->off_err), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *bad = err != 0;
   return CFD_OK;
 }
 
@@ -1121,7 +1142,15 @@ extern "C" cfd_status cfd_residual(cfd_ctx* c, double* dev_R) {
   a.qout = nullptr;
   a.Rout = dev_R;
   a.mode = MODE_RESIDUAL;
-  return launch_stage_all(c, a, c->stream, false);
+  if ((s = launch_stage_all(c, a, c->stream, false)) != CFD_OK) return s;
+  if (c->cfg.debug_flags & CFD_CHECK_FINITE) {
+    bool bad = false;
+    if ((s = debug_clear(c)) != CFD_OK) return s;
+    HIP_TRY(c, launch_check_packed(dev_R, (long long)c->nvar * c->ncells, c->dptr<int>(c->off_err), c->stream));
+    if ((s = debug_flagged(c, &bad)) != CFD_OK) return s;
+    if (bad) return fail(c, CFD_ERR_NONFINITE, "the residual has a non-finite entry");
+  }
+  return CFD_OK;
 }
 
 extern "C" cfd_status cfd_residual_norms(cfd_ctx* c, double* dev_R, double* dev_norms) {
@@ -1154,14 +1183,25 @@ extern "C" cfd_status cfd_rk_step(cfd_ctx* c, int nsteps, double* dev_dt_last) {
   if (nsteps < 0) return CFD_ERR_ARG;
   if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
   if ((s = ensure_dt(c)) != CFD_OK) return s;
-  const bool graph = c->use_graph && c->exec_mode == CFD_EXEC_BATCHED && !c->profiling;
+  const bool check = c->cfg.debug_flags & CFD_CHECK_FINITE;
+  const bool graph = c->use_graph && c->exec_mode == CFD_EXEC_BATCHED && !c->profiling && !c->cfg.debug_flags;
   if (graph && !c->graph_valid && nsteps > 0)
     if ((s = build_graph(c)) != CFD_OK) return s;
   for (int n = 0; n < nsteps; ++n) {
+    if (check && (s = debug_clear(c)) != CFD_OK) return s;
     if (graph) {
       HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
     } else if ((s = enqueue_step(c, c->stream, c->profiling)) != CFD_OK) {
       return s;
+    }
+    if (check) {
+      bool bad = false;
+      if ((s = debug_flagged(c, &bad)) != CFD_OK) return s;
+      if (bad)
+        return fail(c, CFD_ERR_NONFINITE,
+                    "step %d of %d: a stage produced a non-positive or non-finite density or pressure "
+                    "(or a non-finite velocity)",
+                    n + 1, nsteps);
     }
   }
   if (dev_dt_last) HIP_TRY(c, launch_copy_dt(c->dptr<double>(c->off_dt), dev_dt_last, c->stream));
@@ -1501,12 +1541,14 @@ extern "C" cfd_status cfd_rk_step_record(cfd_ctx* c, void* dev_stages) {
   const int M = c->cfg.rk_stages;
   double* slot0 = static_cast<double*>(dev_stages);
   double* A = c->stA();
-  if ((s = fill_ghosts(c, A, hs)) != CFD_OK) return s;
+  // stage_prep: ghost fill, and the viscous residual of the stage input in a
+  // Navier-Stokes context, exactly as enqueue_step does
+  if ((s = stage_prep(c, A, hs)) != CFD_OK) return s;
   HIP_TRY(c, hipMemcpyAsync(slot0, A, (size_t)c->state_doubles * 8, hipMemcpyDeviceToDevice, hs));
   const double* in = A;
   for (int k = 1; k <= M; ++k) {
     double* out = (k == M) ? A : slot0 + (size_t)k * c->state_doubles;
-    if (k > 1 && (s = fill_ghosts(c, const_cast<double*>(in), hs)) != CFD_OK) return s;
+    if (k > 1 && (s = stage_prep(c, const_cast<double*>(in), hs)) != CFD_OK) return s;
     StageArgs a = stage_args(c);
     a.qin = in;
     a.q0 = A;

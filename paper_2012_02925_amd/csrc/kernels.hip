@@ -1,6 +1,7 @@
 // Device kernels of the Euler hot path and their host-side launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "cfd_internal.h"
@@ -588,6 +589,80 @@ __global__ void freeze_kernel(FreezeArgs a) {
       phi[(d * NV + v) * vs + p] = f;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// debug checks (cfd_config.debug_flags)
+
+// CFD_NAN_GHOSTS: quiet NaN into every cell of the ghost region (i in
+// [-2, ni+2) x j in [-2, nj+2) [x k in [-2, nk+2)] minus the interior) of
+// every array of a state buffer, before the ghost fill, so a ghost value the
+// fill does not provide (or a corner ghost, never filled) surfaces as NaN
+// wherever a kernel reads it.
+template <int DIM>
+__global__ void __launch_bounds__(256) nan_ghosts_kernel(CellArgs a) {
+  constexpr int NV = DIM + 2;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long ex = B.ni + 4, ey = B.nj + 4, ez = DIM == 3 ? B.nk + 4 : 1;
+  if (n >= ex * ey * ez) return;
+  const int i = (int)(n % ex) - 2;
+  const int j = (int)((n / ex) % ey) - 2;
+  const int k = DIM == 3 ? (int)(n / (ex * ey)) - 2 : 0;
+  if (i >= 0 && i < B.ni && j >= 0 && j < B.nj && (DIM == 2 || (k >= 0 && k < B.nk))) return;
+  double* q = a.dst + B.origin + pidx(B, i, j, k);
+  const double qnan = __longlong_as_double(0x7ff8000000000000LL);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) q[v * B.vstride] = qnan;
+}
+
+// CFD_CHECK_FINITE: flag (*a.err |= 1) an interior cell of a primitive state
+// buffer whose density or pressure is not positive and finite or whose
+// velocity is not finite.
+template <int DIM>
+__global__ void __launch_bounds__(256) check_state_kernel(CellArgs a) {
+  constexpr int NV = DIM + 2;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!cell_of(B, c, i, j, k)) return;
+  const double* q = a.src + B.origin + pidx(B, i, j, k);
+  const double r = q[0], p = q[(NV - 1) * B.vstride];
+  bool ok = r > 0.0 && p > 0.0 && isfinite(r) && isfinite(p);
+#pragma unroll
+  for (int v = 1; v < NV - 1; ++v) ok = ok && isfinite(q[v * B.vstride]);
+  if (!ok) atomicOr(a.err, 1);
+}
+
+// CFD_CHECK_FINITE: flag a non-finite entry of a packed array (n doubles).
+__global__ void __launch_bounds__(256) check_packed_kernel(const double* x, long long n, int* err) {
+  bool ok = true;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    ok = ok && isfinite(x[e]);
+  if (!ok) atomicOr(err, 1);
+}
+
+hipError_t launch_nan_ghosts(int dim, const CellArgs& a, long long max_padded, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(nan_ghosts_kernel<2>, cell_grid(max_padded, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(nan_ghosts_kernel<3>, cell_grid(max_padded, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(check_state_kernel<2>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(check_state_kernel<3>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_packed(const double* x, long long n, int* err, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(check_packed_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, err);
+  return hipGetLastError();
 }
 
 hipError_t launch_freeze(int dim, const FreezeArgs& a, long long max_padded, int nblocks, hipStream_t s) {

@@ -14,8 +14,9 @@ from .capi import check, dptr, int2
 F64 = torch.float64
 
 
-def config_from_scheme(dim, scheme):
+def config_from_scheme(dim, scheme, debug_flags=0):
     cfg = capi.CfdConfig()
+    cfg.debug_flags = int(debug_flags)
     cfg.dim = dim
     cfg.gamma = scheme.gamma
     cfg.limiter = capi.LIM[scheme.limiter]
@@ -44,7 +45,7 @@ def config_from_scheme(dim, scheme):
 class Solver:
     """One context: blocks, boundary patches, connections and a bound workspace."""
 
-    def __init__(self, dim, scheme, device="cuda"):
+    def __init__(self, dim, scheme, device="cuda", debug_flags=0):
         self.lib = capi.load()
         self.dim = dim
         self.nvar = dim + 2
@@ -52,12 +53,13 @@ class Solver:
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         self.stream = torch.cuda.current_stream(self.device)
-        self.cfg = config_from_scheme(dim, scheme)
+        self.cfg = config_from_scheme(dim, scheme, debug_flags)
         ctx = ctypes.c_void_p()
         check(self.lib.cfd_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.stream.cuda_stream),
                                   ctypes.byref(ctx)))
         self.ctx = ctx
         self.workspace = None
+        self.has_state = False  # a solution has been set (set_state*, load_state)
         self._record_pool = []
         self.block_shapes = []
         self.patch_ids = []
@@ -65,8 +67,8 @@ class Solver:
 
     # -- construction ------------------------------------------------------
     @classmethod
-    def from_case(cls, case, device="cuda", state=True, adjoint=False, freezing=False):
-        s = cls(case.dim, case.scheme, device)
+    def from_case(cls, case, device="cuda", state=True, adjoint=False, freezing=False, debug_flags=0):
+        s = cls(case.dim, case.scheme, device, debug_flags)
         if adjoint:
             s.enable_adjoint()
         if freezing:
@@ -133,10 +135,12 @@ class Solver:
     def set_state(self, Q):
         Q = Q.to(device=self.device, dtype=F64).contiguous()
         self._check(self.lib.cfd_set_state(self.ctx, dptr(Q)))
+        self.has_state = True
 
     def set_state_primitive(self, q):
         q = q.to(device=self.device, dtype=F64).contiguous()
         self._check(self.lib.cfd_set_state_primitive(self.ctx, dptr(q)))
+        self.has_state = True
 
     def get_state(self):
         Q = torch.empty((self.nvar, self.ncells), dtype=F64, device=self.device)
@@ -236,6 +240,14 @@ class Solver:
     def ninflow(self):
         return sum(1 for k in self.patch_kinds if k == "sup_inflow")
 
+    def inflow_slot(self, patch_id):
+        """Row of a supersonic-inflow patch in the inflow cotangent arrays
+        (the inflow patches in patch-id order)."""
+        inflow = sorted(pid for pid, k in zip(self.patch_ids, self.patch_kinds) if k == "sup_inflow")
+        if patch_id not in inflow:
+            raise ValueError("patch %d is not a supersonic-inflow patch" % patch_id)
+        return inflow.index(patch_id)
+
     def adjoint_reset(self):
         self._check(self.lib.cfd_adjoint_reset(self.ctx))
 
@@ -306,6 +318,7 @@ class Solver:
 
     def load_state(self, buf):
         self._check(self.lib.cfd_load_state(self.ctx, dptr(buf)))
+        self.has_state = True
 
     def pack_nodes(self, node_arrays):
         """Per-block node arrays (dim, ...) -> concatenated (dim, nnodes) device tensor."""

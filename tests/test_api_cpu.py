@@ -312,3 +312,43 @@ def test_tile_lists_cover_every_cell_once():
         lib.cfd_query(ctx, capi.Q["ntiles"], ctypes.byref(v))
         assert v.value >= math.ceil(40 / tx) * math.ceil(36 / ty)
     lib.cfd_destroy(ctx)
+
+
+def test_debug_flags_validation():
+    capi, lib = _lib()
+    ctx = ctypes.c_void_p()
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, debug_flags=4)), None, ctypes.byref(ctx)) == -1
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, debug_flags=-1)), None, ctypes.byref(ctx)) == -1
+    for flags in (0, capi.CHECK_FINITE, capi.NAN_GHOSTS, capi.CHECK_FINITE | capi.NAN_GHOSTS):
+        ctx = _ctx(capi, lib, debug_flags=flags)
+        _add(capi, lib, ctx, 8, 6)
+        _periodic(capi, lib, ctx, 0, 8, 6)
+        n = ctypes.c_size_t()
+        assert lib.cfd_finalize(ctx, ctypes.byref(n)) == 0
+        lib.cfd_destroy(ctx)
+
+
+def test_config_struct_layout_matches_header(tmp_path):
+    """The ctypes mirror of cfd_config has the C struct's size and field
+    offsets (compiled from the header with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_2012_02925_amd import capi
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    fields = [f for f, _ in capi.CfdConfig._fields_]
+    src = tmp_path / "layout.c"
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "cfdhip.h"', "int main(void) {",
+             '  printf("%zu\\n", sizeof(cfd_config));']
+    for f in fields:
+        lines.append('  printf("%%zu\\n", offsetof(cfd_config, %s));' % f)
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(capi.CfdConfig)
+    for f, off in zip(fields, out[1:]):
+        assert getattr(capi.CfdConfig, f).offset == off, f
