@@ -1,7 +1,8 @@
 """torch.autograd bindings of the hand-written adjoint.
 
 ResidualFn          R(Q) as a differentiable op: forward cfd_residual,
-                    backward cfd_residual_vjp.
+                    backward cfd_residual_vjp (the solver's own state is put
+                    back after each pass).
 UnrolledWallPressure J(theta, X) = integrated wall pressure after n Runge-Kutta
                     steps from the uniform state theta (inflow state, also the
                     inflow boundary value) on nodes X.  Forward keeps a
@@ -20,10 +21,16 @@ import torch
 
 
 class ResidualFn(torch.autograd.Function):
+    """R(Q) at the state Q (packed conservative, (nvar, ncells)).  Both passes
+    evaluate at Q through the solver's context and then put back the state
+    the solver held before (bit-exact copy), so calling this op does not
+    disturb a run in progress."""
+
     @staticmethod
     def forward(ctx, Q, solver):
-        solver.set_state(Q)
-        R = solver.residual()
+        with _state_kept(solver):
+            solver.set_state(Q)
+            R = solver.residual()
         ctx.solver = solver
         ctx.save_for_backward(Q)
         return R
@@ -32,9 +39,28 @@ class ResidualFn(torch.autograd.Function):
     def backward(ctx, Rbar):
         (Q,) = ctx.saved_tensors
         s = ctx.solver
-        s.set_state(Q)
-        Qbar, _, _ = s.residual_vjp(Rbar.contiguous())
+        with _state_kept(s):
+            s.set_state(Q)
+            Qbar, _, _ = s.residual_vjp(Rbar.contiguous())
         return Qbar, None
+
+
+class _state_kept:
+    """Save the solver's current state (if it holds one) and restore it on exit."""
+
+    def __init__(self, solver):
+        self.s = solver
+        self.buf = None
+
+    def __enter__(self):
+        if self.s.has_state:
+            self.buf = self.s.save_state()
+        return self
+
+    def __exit__(self, *exc):
+        if self.buf is not None:
+            self.s.load_state(self.buf)
+        return False
 
 
 def residual(solver, Q):
@@ -50,6 +76,7 @@ class UnrolledWallPressure(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, nodes, solver, nsteps, every, inflow_patch):
         s = solver
+        s.inflow_slot(inflow_patch)  # rejects a patch that is not a supersonic inflow
         s.set_nodes(nodes.detach())
         th = [float(x) for x in theta.detach().cpu()]
         s.set_bc_params(inflow_patch, th)
@@ -69,6 +96,7 @@ class UnrolledWallPressure(torch.autograd.Function):
             s.release_record_buffer(slots)
             slots = None
         ctx.solver, ctx.nsteps, ctx.every, ctx.th = s, nsteps, every, th
+        ctx.slot = s.inflow_slot(inflow_patch)
         ctx.ckpts = ckpts
         ctx.slots, ctx.per, ctx.last = slots, per, last
         ctx.final = s.save_state()
@@ -95,7 +123,7 @@ class UnrolledWallPressure(torch.autograd.Function):
         s.release_record_buffer(slots)
         ctx.slots = None
         Xbar, Tbar = s.adjoint_result(nodes=True, inflow=True)
-        theta_bar = s.uniform_state_vjp(ctx.th, Qbar) + Tbar[0]
+        theta_bar = s.uniform_state_vjp(ctx.th, Qbar) + Tbar[ctx.slot]
         jb = Jbar.to(s.device)
         return (jb * theta_bar).to(ctx.theta_device), (jb * Xbar).reshape(ctx.nodes_shape), None, None, None, None
 

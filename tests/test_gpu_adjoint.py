@@ -278,3 +278,54 @@ def test_residual_vjp_matches_oracle_3d_box():
     Qr, _, _ = _oracle_vjp(case, Rbar)
     for v in range(case.nvar):
         _close(Qb[v], Qr[v], VJP_TOL, "Qbar[%d]" % v)
+
+
+def test_residual_fn_forward_backward_and_state_kept():
+    """ResidualFn (torch.autograd.Function over cfd_residual / cfd_residual_vjp):
+    forward equals cfd_residual at Q, torch.autograd.grad through it equals the
+    oracle's autograd VJP, and the solver's own state is unchanged by both
+    passes (bit for bit)."""
+    from paper_2012_02925_amd.autograd import ResidualFn
+    _say("case: ramp 40x26, ResidualFn")
+    case = _ramp(40, 26, seed=4)
+    s = _solver(case)
+    held = s.get_state().clone()  # the solver's state: the case's initial state
+    Q = _conservative_from_prims(_ramp(40, 26, seed=5)).to("cuda:0").requires_grad_(True)
+    R = ResidualFn.apply(Q, s)
+    torch.cuda.synchronize()
+    assert torch.equal(s.get_state(), held)
+    # forward = cfd_residual at Q
+    from paper_2012_02925_amd.solver import Solver
+    s2 = Solver.from_case(case, device="cuda:0", adjoint=True)
+    s2.set_state(Q.detach())
+    assert torch.equal(R.detach(), s2.residual())
+    rng = np.random.default_rng(6)
+    Rbar = torch.tensor(rng.standard_normal((case.nvar, case.ncells)))
+    (g,) = torch.autograd.grad(R, Q, grad_outputs=Rbar.to("cuda:0"))
+    torch.cuda.synchronize()
+    assert torch.equal(s.get_state(), held)
+    case_q = _ramp(40, 26, seed=5)
+    Qr, _, _ = _oracle_vjp(case_q, Rbar)
+    for v in range(case.nvar):
+        _close(g[v], Qr[v], VJP_TOL, "ResidualFn grad Q[%d]" % v)
+    s.close()
+    s2.close()
+
+
+def test_rk_step_record_matches_rk_step_navier_stokes():
+    """cfd_rk_step_record advances exactly like cfd_rk_step, also with the
+    viscous residual recomputed for every stage input (laminar Navier-Stokes),
+    and leaves the ghost-filled stage inputs in the caller's slots."""
+    from paper_2012_02925_amd.solver import Solver
+    case = synth.jittered_periodic_square(48, 40, seed=3)
+    case.scheme.viscosity = 0.01
+    a = Solver.from_case(case, device="cuda:0")
+    b = Solver.from_case(case, device="cuda:0")
+    slots, per = b.stage_record_buffer(1)
+    for _ in range(3):
+        a.rk_step(1)
+        b.rk_step_record(slots[:per])
+    torch.cuda.synchronize()
+    assert torch.equal(a.get_state(), b.get_state())
+    a.close()
+    b.close()
