@@ -7,7 +7,8 @@ Tolerances (written here once, used by every parity test):
     residual of variable v is the flux of the reference state through all
     faces of a cell without cancellation,
         R_scale,v = Q_ref,v (|V_ref| + c_ref) max_cells (sum_f |S_f|) / Omega,
-    and every variable must satisfy max|R_gpu,v - R_oracle,v| <= 1e-12 R_scale,v.
+    and every variable must satisfy max|R_gpu,v - R_oracle,v| <= 1e-12 R_scale,v
+    (tested at RES_TOL = 1e-13, below).
     (The residual itself is a difference of face fluxes that can be 1e4 times
     smaller than the fluxes, e.g. the 1 % density bump; one rounding step in
     one face flux then already exceeds 1e-12 of the residual, whatever the
@@ -24,7 +25,12 @@ import torch
 import oracle
 from oracle import gas
 
-RES_TOL = 1e-12
+# The bar of the method is 1e-12 of the reference flux scale; the tests hold
+# the kernels to 1e-13 (the largest error observed on any parity case is
+# 2.7e-14 of the scale, a Navier-Stokes channel; the Euler cases stay below
+# 2e-14), so a loss of accuracy of one order in the hardware reciprocal or
+# square-root refinements shows up as a failure.
+RES_TOL = 1e-13
 STATE_TOL = 1e-10
 
 
