@@ -27,10 +27,8 @@ struct ViscArgs {
   const ChunkDev* chunks;  // ghost-fill chunk list 1 (transfer packs and physical patches)
   const double* nodes;     // grid nodes [coord][node]
   const double* metric;
-  double* centers;         // padded arrays from BlockDev::corigin: dim cell-centre coordinates,
-                           // the temperature, then dim * (dim+1) viscous face fluxes
+  double* centers;         // padded arrays from BlockDev::corigin: dim cell-centre coordinates
   double* npos;            // pseudo-node positions [coord][node]
-  double* nval;            // pseudo-node values [(u.., T)][node]
   const double* q;         // primitive state buffer, face ghosts filled
   double* rv;              // viscous residual [(momentum.., energy)][cell], packed
   double mu;               // viscosity
@@ -46,12 +44,11 @@ void viscous_tile_shape(int dim, int* tx, int* ty, int* tk);
 
 hipError_t launch_cell_centers(int dim, const ViscArgs& a, long long max_cells, int nblocks, hipStream_t s);
 hipError_t launch_ghost_centers(int dim, const ViscArgs& a, int nchunks, hipStream_t s);
-// mode 0: pseudo-node positions from the centres; 1: values from the state
-hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, int mode, long long max_nodes, int nblocks, hipStream_t s);
-// Per stage: one fused tiled pass (2D or 3D; with no tile list the 2D
-// chain of temperatures, pseudo-node values, face fluxes and divergence).  max_padded bounds (ni+2)(nj+2)(nk+2), max_nodes the
-// node count of a block.
-hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_padded, long long max_nodes, long long max_cells,
-                          int nblocks, hipStream_t s);
+// pseudo-node positions from the centres (set-up); max_nodes bounds the node
+// count of a block
+hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, long long max_nodes, int nblocks, hipStream_t s);
+// Per stage: one fused tiled pass over the tile list (2D or 3D); the pass
+// stages the pseudo-node values of (u.., T) of each tile in LDS itself.
+hipError_t launch_viscous(int dim, const ViscArgs& a, hipStream_t s);
 
 }  // namespace cfd

@@ -140,19 +140,17 @@ __global__ void __launch_bounds__(CHUNK) ghost_centers_kernel(ViscArgs a) {
   for (int c = 0; c < DIM; ++c) cg[c * B.vstride] = c0[c] - 2.0 * dn * (S[c] / len);
 }
 
-// Pseudo-node (I, J, K): mean over the cells (I-1+ai, J-1+aj, K-1+ak) with at
-// most one index outside the block.
+// Pseudo-node (I, J, K) position: mean centre of the cells
+// (I-1+ai, J-1+aj, K-1+ak) with at most one index outside the block.
 template <int DIM>
-__global__ void __launch_bounds__(256) pseudo_nodes_kernel(ViscArgs a, int mode) {
-  constexpr int NW = DIM + 1;
+__global__ void __launch_bounds__(256) pseudo_nodes_kernel(ViscArgs a) {
   const BlockDev B = a.blocks[blockIdx.y];
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   int I, J, K;
   if (!decode3(n, B.ni + 1, B.nj + 1, DIM == 3 ? B.nk + 1 : 1, I, J, K)) return;
-  const int nw = mode == 0 ? DIM : DIM + 1;
-  double acc[NW];
+  double acc[DIM];
 #pragma unroll
-  for (int w = 0; w < NW; ++w) acc[w] = 0.0;
+  for (int w = 0; w < DIM; ++w) acc[w] = 0.0;
   int cnt = 0;
 #pragma unroll
   for (int ai = 0; ai < 2; ++ai)
@@ -165,38 +163,12 @@ __global__ void __launch_bounds__(256) pseudo_nodes_kernel(ViscArgs a, int mode)
         if (out > 1) continue;
         const long long p = pidx(B, I - 1 + ai, J - 1 + aj, DIM == 3 ? K - 1 + ak : 0);
         ++cnt;
-        if (mode == 0) {
-          const double* C = a.centers + B.corigin + p;
+        const double* C = a.centers + B.corigin + p;
 #pragma unroll
-          for (int c = 0; c < DIM; ++c) acc[c] += C[c * B.vstride];
-        } else {
-          const double* q = a.q + B.origin + p;
-#pragma unroll
-          for (int c = 0; c < DIM; ++c) acc[c] += q[(1 + c) * B.vstride];
-          acc[DIM] += a.centers[B.corigin + DIM * B.vstride + p];
-        }
+        for (int c = 0; c < DIM; ++c) acc[c] += C[c * B.vstride];
       }
   const long long nn = node_index(B, I, J, K);
-  double* out = mode == 0 ? a.npos : a.nval;
-  for (int w = 0; w < nw; ++w) out[w * B.nnode_total + nn] = acc[w] / (double)cnt;
-}
-
-// Temperature T = gamma p / rho of every interior and face-ghost cell (array
-// DIM of the centre buffer), so each cell divides once per stage.
-template <int DIM>
-__global__ void __launch_bounds__(256) temperature_kernel(ViscArgs a) {
-  const BlockDev B = a.blocks[blockIdx.y];
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (!decode3(n, B.ni + 2, B.nj + 2, DIM == 3 ? B.nk + 2 : 1, i, j, k)) return;
-  i -= 1;
-  j -= 1;
-  if (DIM == 3) k -= 1;
-  const int out = (i < 0 || i >= B.ni) + (j < 0 || j >= B.nj) + (DIM == 3 ? (k < 0 || k >= B.nk) : 0);
-  if (out > 1) return;
-  const long long p = pidx(B, i, j, k);
-  const double* q = a.q + B.origin + p;
-  a.centers[B.corigin + DIM * B.vstride + p] = a.gamma * q[(DIM + 1) * B.vstride] / q[0];
+  for (int w = 0; w < DIM; ++w) a.npos[w * B.nnode_total + nn] = acc[w] / (double)cnt;
 }
 
 // Green's-theorem gradient of (u.., T) on one face over its dual volume: the
@@ -281,97 +253,11 @@ __device__ __forceinline__ void viscous_flux(const double (*G)[DIM], const doubl
   F[DIM] = energy;
 }
 
-// Each face once: thread (i, j, k) over the cells and first high ghosts
-// computes the low face of direction d of cell (i, j, k) where that face
-// exists (index along d in 0..n_d, interior along the others) and stores
-// F_v . S in the face arrays (centre buffer, array DIM + 1 + d * (DIM+1) + v).
-template <int DIM>
-__global__ void __launch_bounds__(256) viscous_faces_kernel(ViscArgs a) {
-  using ML = MetricLayout<DIM>;
-  constexpr int NW = DIM + 1;
-  constexpr int NP = DIM == 3 ? 4 : 2;
-  const BlockDev B = a.blocks[blockIdx.y];
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (!decode3(n, B.ni + 1, B.nj + 1, DIM == 3 ? B.nk + 1 : 1, i, j, k)) return;
-  const long long vs = B.vstride;
-  const double* met = a.metric + B.morigin;
-  const double* cen = a.centers + B.corigin;
-  const long long pr = pidx(B, i, j, k);
-#pragma unroll 1
-  for (int d = 0; d < DIM; ++d) {
-    const bool ok = (d == 0 || i < B.ni) && (d == 1 || j < B.nj) && (DIM == 2 || d == 2 || k < B.nk);
-    if (!ok) continue;
-    const int di = d == 0, dj = d == 1, dk = d == 2;
-    const long long pl = pidx(B, i - di, j - dj, k - dk);
-    double D[DIM], VL[NW], VR[NW], S[DIM];
-#pragma unroll
-    for (int x = 0; x < DIM; ++x) {
-      D[x] = cen[x * vs + pr] - cen[x * vs + pl];
-      S[x] = met[ML::S(d, x) * vs + pr];
-      VL[x] = a.q[B.origin + (1 + x) * vs + pl];
-      VR[x] = a.q[B.origin + (1 + x) * vs + pr];
-    }
-    VL[DIM] = cen[DIM * vs + pl];
-    VR[DIM] = cen[DIM * vs + pr];
-    double P[NP][DIM], W[NP][NW];
-#pragma unroll
-    for (int m = 0; m < NP; ++m) {
-      // cyclic order over the tangential offsets (o1, o2): (0,0) (1,0) (1,1) (0,1),
-      // tangential axes in increasing order
-      const int o1 = (m == 1 || m == 2) ? 1 : 0, o2 = m >= 2 ? 1 : 0;
-      const int ni_ = i + (d == 0 ? 0 : o1);
-      const int nj_ = j + (d == 0 ? o1 : (d == 1 ? 0 : o2));
-      const int nk_ = DIM == 3 ? k + (d == 2 ? 0 : o2) : 0;
-      const long long nn = node_index(B, ni_, nj_, nk_);
-#pragma unroll
-      for (int x = 0; x < DIM; ++x) P[m][x] = a.npos[x * B.nnode_total + nn];
-#pragma unroll
-      for (int v = 0; v < NW; ++v) W[m][v] = a.nval[v * B.nnode_total + nn];
-    }
-    double G[NW][DIM], uf[DIM], F[NW];
-    dual_gradient<DIM>(D, VL, VR, P, W, G);
-#pragma unroll
-    for (int x = 0; x < DIM; ++x) uf[x] = 0.5 * (VL[x] + VR[x]);
-    viscous_flux<DIM>(G, uf, S, a.mu, a.kcond, F);
-    double* fo = a.centers + B.corigin + (DIM + 1 + d * NW) * vs + pr;
-#pragma unroll
-    for (int v = 0; v < NW; ++v) fo[v * vs] = F[v];
-  }
-}
-
-// Rv = (1/Omega) sum_d (F_d(high face) - F_d(low face)), packed per cell.
-template <int DIM>
-__global__ void __launch_bounds__(256) viscous_divergence_kernel(ViscArgs a) {
-  using ML = MetricLayout<DIM>;
-  constexpr int NW = DIM + 1;
-  const BlockDev B = a.blocks[blockIdx.y];
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  if (!cell_coords(B, c, i, j, k)) return;
-  const long long vs = B.vstride;
-  const long long p = pidx(B, i, j, k);
-  const double* f = a.centers + B.corigin + (DIM + 1) * vs + p;
-  const long long step[3] = {1, B.pi, (long long)B.pi * B.pj};
-  const double iv = a.metric[B.morigin + ML::INVVOL * vs + p];
-#pragma unroll
-  for (int v = 0; v < NW; ++v) {
-    double acc = 0.0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const double* fd = f + (d * NW + v) * vs;
-      acc += fd[step[d]] - fd[0];
-    }
-    a.rv[v * B.ncell_total + B.packed + c] = acc * iv;
-  }
-}
-
 // Fused 3D pass over a tile of VT_X x VT_Y columns and up to VT_K planes:
 // the plane pair (k, k+1) of cells (with a one-cell halo ring) and of
 // pseudo-nodes is staged in LDS while the tile marches in k; every face of
 // the tile is computed once (x- and y-faces into LDS, the column's k-faces in
-// registers) and each cell writes its Rv.  Same arithmetic as the per-face
-// kernels above, without their repeated global reads.
+// registers) and each cell writes its Rv.
 constexpr int VT_X = 16, VT_Y = 16, VT_K = 32;
 
 __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
@@ -765,11 +651,11 @@ hipError_t launch_ghost_centers(int dim, const ViscArgs& a, int nchunks, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, int mode, long long max_nodes, int nblocks, hipStream_t s) {
+hipError_t launch_pseudo_nodes(int dim, const ViscArgs& a, long long max_nodes, int nblocks, hipStream_t s) {
   if (dim == 2)
-    hipLaunchKernelGGL(pseudo_nodes_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a, mode);
+    hipLaunchKernelGGL(pseudo_nodes_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(pseudo_nodes_kernel<3>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a, mode);
+    hipLaunchKernelGGL(pseudo_nodes_kernel<3>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -779,18 +665,12 @@ void viscous_tile_shape(int dim, int* tx, int* ty, int* tk) {
   *tk = dim == 2 ? 1 : VT_K;
 }
 
-hipError_t launch_viscous(int dim, const ViscArgs& a, long long max_padded, long long max_nodes, long long max_cells,
-                          int nblocks, hipStream_t s) {
-  if (dim == 2 && a.ntiles > 0) {
+hipError_t launch_viscous(int dim, const ViscArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  if (dim == 2)
     hipLaunchKernelGGL(viscous_tile2d_kernel, dim3(a.ntiles), dim3(VT2 * VT2), 0, s, a);
-  } else if (dim == 2) {
-    hipLaunchKernelGGL(temperature_kernel<2>, grid_of(max_padded, nblocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(pseudo_nodes_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a, 1);
-    hipLaunchKernelGGL(viscous_faces_kernel<2>, grid_of(max_nodes, nblocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(viscous_divergence_kernel<2>, grid_of(max_cells, nblocks), dim3(256), 0, s, a);
-  } else if (a.ntiles > 0) {
+  else
     hipLaunchKernelGGL(viscous_tile_kernel, dim3(a.ntiles), dim3(VT_X * VT_Y), 0, s, a);
-  }
   return hipGetLastError();
 }
 
