@@ -10,7 +10,9 @@ physical patches, unpack, fused residual/update kernel; the last stage also
 reduces the next time step).  Inputs are resident in HBM before timing.
 
 Prints one JSON line:
-  value      FP64 cell-updates per second per RK stage (cells * stages * steps / time)
+  value      FP64 cell-updates per second per RK stage (cells * stages * steps / time),
+             the median over --repeats timed regions of exactly --steps steps
+             (captured step graph; each region bracketed by synchronisation)
   roofline   the fused stage kernel against HBM bandwidth: algorithmic bytes
              per launch (190 B per cell-stage in 3D, 128 B in 2D, see the
              design notes) / mean launch time from HIP events recorded on the
@@ -18,9 +20,12 @@ Prints one JSON line:
   fp64       the same launches against the FP64 vector peak, with the FP64
              operations per launch counted by rocprofv3 (FMA = 2) for this
              kernel source, when such a count is on record
-  copy_gbs   a 1 GiB device-to-device copy on the same GPU (a practical HBM
-             ceiling, for context)
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
+  copy_gbs   a 1 GiB device-to-device copy on the same GPU (for context)
+  stream_ceiling  a plain streaming kernel with the stage kernel's traffic per
+             cell (20 doubles read, 5 written), the practical HBM ceiling the
+             roofline also reports its fraction of
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload,
+             with all host threads and with one
 """
 import argparse
 import hashlib
@@ -90,9 +95,10 @@ def make_case(workload, n):
     raise SystemExit("unknown workload %s" % workload)
 
 
-def cpu_baseline(workload, target_s=12.0):
+def cpu_baseline(workload, target_s=10.0):
     """The oracle, as it is, on a reduced copy of the workload: RK steps until
-    at least target_s seconds of CPU work; returns cell-stages/s."""
+    at least target_s seconds of CPU work, once with all of torch's host
+    threads and once with one thread; returns cell-stages/s for both."""
     import torch
 
     import oracle
@@ -105,26 +111,71 @@ def cpu_baseline(workload, target_s=12.0):
     else:
         case = make_case(workload, 128) if workload != "patchwork" else synth.patchwork(seed=0, side_lo=16, side_hi=64)
         sample = case.name + " (reduced size)"
-    P = oracle.Problem(case)
-    Q = P.initial_state()
-    met = P.metrics()
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        Q, _ = P.rk_step(Q, met)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s:
-            break
-    rate = case.ncells * P.stages * steps / el
-    return {"value": rate, "unit": "cell-updates/s per RK stage", "cores": torch.get_num_threads(),
-            "kind": "oracle", "sample": "%s, %d RK steps in %.1f s" % (sample, steps, el)}
+
+    def timed(threads):
+        old = torch.get_num_threads()
+        torch.set_num_threads(threads)
+        try:
+            P = oracle.Problem(case)
+            Q = P.initial_state()
+            met = P.metrics()
+            steps = 0
+            t0 = time.perf_counter()
+            while True:
+                Q, _ = P.rk_step(Q, met)
+                steps += 1
+                el = time.perf_counter() - t0
+                if el >= target_s:
+                    break
+            return case.ncells * P.stages * steps / el, steps, el
+        finally:
+            torch.set_num_threads(old)
+
+    cores = torch.get_num_threads()
+    rate, steps, el = timed(cores)
+    rate1, steps1, el1 = timed(1)
+    return {"value": rate, "unit": "cell-updates/s per RK stage", "cores": cores, "kind": "oracle",
+            "sample": "%s, %d RK steps in %.1f s on %d threads" % (sample, steps, el, cores),
+            "single_thread": {"value": rate1, "cores": 1,
+                              "sample": "%s, %d RK steps in %.1f s on 1 thread" % (sample, steps1, el1)},
+            "host_logical_cpus": os.cpu_count()}
 
 
-def bench_batching(steps=20, warmup=2):
+def stream_ceiling(cells, reps=10):
+    """Practical HBM ceiling for the stage kernel's traffic: a plain streaming
+    kernel (cfd_stream_probe) reading 20 and writing 5 arrays of `cells`
+    doubles (the 3D stage kernel's per-cell traffic after the first stage),
+    with 8-byte and with 16-byte accesses; GB/s of each."""
+    import ctypes
+
+    import torch
+
+    from paper_2012_02925_amd import capi
+
+    lib = capi.load()
+    src = torch.ones(20 * cells, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty(5 * cells, dtype=torch.float64, device="cuda:0")
+    st = torch.cuda.current_stream()
+    out = {"reads": 20, "writes": 5, "cells": cells}
+    for vec in (1, 2):
+        ms = ctypes.c_double()
+        capi.check(lib.cfd_stream_probe(20, 5, vec, capi.dptr(src), capi.dptr(dst), cells, reps,
+                                        ctypes.c_void_p(st.cuda_stream), ctypes.byref(ms)))
+        out["gbs_%dB_access" % (8 * vec)] = 25.0 * 8 * cells / (ms.value * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    out["gbs"] = max(out["gbs_8B_access"], out["gbs_16B_access"])
+    return out
+
+
+def bench_batching(steps=20, warmup=2, repeats=3):
     """64-block patchwork (block sides uniform in [64, 512], all faces
-    connected): one launch per block per phase vs. batched launches inside a
-    captured hipGraph.  Same kernels, same tiles, bitwise-identical results."""
+    connected): one launch per block per phase (no graph) vs. batched launches
+    over the tile list of every block, without and with the captured hipGraph
+    of one RK step; tile shape autotuned for the batched launch.  Same kernels,
+    bitwise-identical results.  Median over `repeats` timed regions each."""
+    import statistics
+
     import torch
 
     import synth
@@ -133,21 +184,34 @@ def bench_batching(steps=20, warmup=2):
     case = synth.patchwork(seed=0)
     out = {"workload": case.name, "blocks": len(case.blocks), "cells": case.ncells}
     results = {}
-    for mode, graph in (("per_block", False), ("batched", True)):
+    variant = None
+    for mode, graph, label in (("batched", False, "batched"), ("batched", True, "batched_graph"),
+                               ("per_block", False, "per_block")):
         s = Solver.from_case(case, device="cuda:0")
+        if variant is None:
+            variant = s.autotune(reps=3)
+            out["tile_variant"] = variant
+        else:
+            s.set_variant(variant)
         s.set_exec(mode, graph)
         s.rk_step(warmup)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.rk_step(steps)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        results[mode] = case.ncells * case.scheme.rk_stages * steps / el
-        out[mode + "_ms_per_step"] = el * 1e3 / steps
+        times = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            s.rk_step(steps)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        el = statistics.median(times)
+        results[label] = case.ncells * case.scheme.rk_stages * steps / el
+        out[label + "_ms_per_step"] = el * 1e3 / steps
         s.close()
     out["per_block_value"] = results["per_block"]
-    out["batched_graph_value"] = results["batched"]
-    out["speedup"] = results["batched"] / results["per_block"]
+    out["batched_value"] = results["batched"]
+    out["batched_graph_value"] = results["batched_graph"]
+    out["speedup_batching"] = results["batched"] / results["per_block"]
+    out["speedup_batching_and_graph"] = results["batched_graph"] / results["per_block"]
+    out["per_block_mode"] = "one launch per block per phase, no graph"
     out["unit"] = "cell-updates/s per RK stage"
     return out
 
@@ -316,6 +380,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=5, help="timed regions of --steps steps; value = median")
     ap.add_argument("--workload", default="jittered_periodic_box")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -367,23 +432,32 @@ def main():
     s.rk_step(args.warmup)
     torch.cuda.synchronize()
 
-    # timed region: K steps, HIP events around every stage-kernel launch
+    # timed regions: `repeats` times exactly K steps (captured step graph),
+    # each bracketed by synchronisation; the value is the median
+    import statistics
+
+    st = s.stream
+    reps = []
+    for _ in range(args.repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(st)
+        s.rk_step(args.steps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps.append({"wall_s": t1 - t0, "event_ms": e0.elapsed_time(e1)})
+    walls = [r["wall_s"] for r in reps]
+    elapsed = statistics.median(walls)
+
+    # kernel timing: K more steps with HIP events around every stage launch
     s.profile(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     s.rk_step(args.steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     kms, launches = s.kernel_time()
     s.profile(False)
-    elapsed = t1 - t0
-
-    # same K steps with the captured hipGraph (reported beside the headline)
-    torch.cuda.synchronize()
-    g0 = time.perf_counter()
-    s.rk_step(args.steps)
-    torch.cuda.synchronize()
-    g1 = time.perf_counter()
 
     stages = case.scheme.rk_stages
     cells = case.ncells
@@ -397,7 +471,12 @@ def main():
     traffic = load_traffic(kname, sha)
     Q = s.get_state()
     finite = bool(torch.isfinite(Q).all().item())
+    variant = s.query("variant")
+    s.close()
+    del s, Q
+    torch.cuda.empty_cache()
     copy_gbs = copy_ceiling_gbs()
+    ceiling = stream_ceiling(cells) if dim == 3 else None
 
     out = {
         "metric": "FP64 cell-updates/s per RK stage + % HBM roofline; adjoint/forward time ratio",
@@ -414,14 +493,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": case.name, "cells": cells, "dim": dim, "limiter": case.scheme.limiter,
                    "flux": "roe", "rk_stages": stages, "dt": "global CFL 0.5, device-side",
-                   "tile_variant": s.query("variant"), "autotuned": chosen is not None},
+                   "tile_variant": variant, "autotuned": chosen is not None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None if traffic is None else traffic["bytes_per_launch"],
                      "kernel": "cfd::stage_kernel", "bytes_per_cell_stage": BYTES_PER_CELL_STAGE[dim],
-                     "mean_launch_ms": mean_launch_s * 1e3, "launches": launches},
+                     "mean_launch_ms": mean_launch_s * 1e3, "launches": launches,
+                     "practical_ceiling_gbs": None if ceiling is None else ceiling["gbs"],
+                     "frac_of_practical_ceiling": None if ceiling is None else achieved / ceiling["gbs"]},
+        "timing": {"repeats": args.repeats, "steps_per_repeat": args.steps,
+                   "ms_per_step_each": [w * 1e3 / args.steps for w in walls],
+                   "event_ms_per_step_each": [r["event_ms"] / args.steps for r in reps],
+                   "median_ms_per_step": elapsed * 1e3 / args.steps,
+                   "spread": (max(walls) - min(walls)) / elapsed,
+                   "captured_step_graph": True},
         "copy_gbs": copy_gbs,
-        "graph_ms_per_step": (g1 - g0) * 1e3 / args.steps,
+        "stream_ceiling": ceiling,
         "state_finite": finite,
         "kernel_source_sha": sha,
     }
@@ -431,9 +518,6 @@ def main():
                        "frac": fl / FP64_VECTOR_PEAK_TFLOPS,
                        "flops_per_cell_stage": traffic["fp64_flops_per_launch"] / cells}
     if not args.no_extras:
-        s.close()
-        del s, Q
-        torch.cuda.empty_cache()
         print("[bench] batching: 64-block patchwork, per-block vs batched+graph", file=sys.stderr, flush=True)
         out["batching"] = bench_batching()
         print("[bench] adjoint: 512^2 ramp, 50 unrolled steps", file=sys.stderr, flush=True)

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcfdhip.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "kernels.hip", "stage2d.hip", "stage3d.hip", "stage3d_fvs.hip", "adjoint.hip", "viscous.hip"]
+SOURCES = ["api.hip", "kernels.hip", "stage2d.hip", "stage3d.hip", "stage3d_fvs.hip", "adjoint.hip", "viscous.hip", "probe.hip"]
 ARCH = os.environ.get("CFDHIP_ARCH", "gfx950")
 
 FLAGS = [
