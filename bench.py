@@ -171,9 +171,11 @@ def stream_ceiling(cells, reps=10):
 def bench_batching(steps=20, warmup=2, repeats=3):
     """64-block patchwork (block sides uniform in [64, 512], all faces
     connected): one launch per block per phase (no graph) vs. batched launches
-    over the tile list of every block, without and with the captured hipGraph
-    of one RK step; tile shape autotuned for the batched launch.  Same kernels,
-    bitwise-identical results.  Median over `repeats` timed regions each."""
+    over the tile list of every block -- one workgroup per tile, or persistent
+    (as many workgroups as the GPU holds, walking the list) -- without and with
+    the captured hipGraph of one RK step; tile shape autotuned for the batched
+    launch.  Same kernels, bitwise-identical results.  Median over `repeats`
+    timed regions each."""
     import statistics
 
     import torch
@@ -186,6 +188,7 @@ def bench_batching(steps=20, warmup=2, repeats=3):
     results = {}
     variant = None
     for mode, graph, label in (("batched", False, "batched"), ("batched", True, "batched_graph"),
+                               ("persistent", False, "persistent"), ("persistent", True, "persistent_graph"),
                                ("per_block", False, "per_block")):
         s = Solver.from_case(case, device="cuda:0")
         if variant is None:
@@ -206,11 +209,11 @@ def bench_batching(steps=20, warmup=2, repeats=3):
         results[label] = case.ncells * case.scheme.rk_stages * steps / el
         out[label + "_ms_per_step"] = el * 1e3 / steps
         s.close()
-    out["per_block_value"] = results["per_block"]
-    out["batched_value"] = results["batched"]
-    out["batched_graph_value"] = results["batched_graph"]
+    for label, rate in results.items():
+        out[label + "_value"] = rate
     out["speedup_batching"] = results["batched"] / results["per_block"]
-    out["speedup_batching_and_graph"] = results["batched_graph"] / results["per_block"]
+    out["speedup_persistent"] = results["persistent"] / results["per_block"]
+    out["speedup_batching_and_graph"] = max(results["batched_graph"], results["persistent_graph"]) / results["per_block"]
     out["per_block_mode"] = "one launch per block per phase, no graph"
     out["unit"] = "cell-updates/s per RK stage"
     return out

@@ -80,7 +80,9 @@ enum {
  * area vectors in direction d. */
 enum { CFD_DT_CFL = 0, CFD_DT_FIXED = 1, CFD_DT_LOCAL = 2 };
 /* execution modes for cfd_set_exec */
-enum { CFD_EXEC_BATCHED = 0, CFD_EXEC_PER_BLOCK = 1 };
+enum { CFD_EXEC_BATCHED = 0, CFD_EXEC_PER_BLOCK = 1, CFD_EXEC_PERSISTENT = 2 };
+/* connected-boundary exchange for cfd_set_ghost_exchange */
+enum { CFD_GHOSTS_DIRECT = 0, CFD_GHOSTS_PACKED = 1 };
 
 typedef struct {
   int dim;              /* 2 or 3 */
@@ -262,10 +264,23 @@ cfd_status cfd_padded_primitives(cfd_ctx* ctx, double* dev_out);
 cfd_status cfd_padded_size(cfd_ctx* ctx, size_t* count);
 
 /* Execution mode of rk_step/residual: CFD_EXEC_BATCHED launches every phase
- * once for all blocks (tile list over every block, grid-stride loop);
- * CFD_EXEC_PER_BLOCK launches each phase once per block.  use_graph != 0
- * captures one Runge-Kutta step in a hipGraph (batched mode only). */
+ * once for all blocks (tile list over every block, one workgroup per tile);
+ * CFD_EXEC_PERSISTENT launches the stage kernel once for all blocks with as
+ * many workgroups as the device holds at once, each walking the tile list
+ * (grid-stride loop); CFD_EXEC_PER_BLOCK launches each phase once per block.
+ * use_graph != 0 captures one Runge-Kutta step in a hipGraph (batched and
+ * persistent modes).  All modes give bit-identical results. */
 cfd_status cfd_set_exec(cfd_ctx* ctx, int mode, int use_graph);
+
+/* Connected-boundary exchange (Sec. 4: ghosts of connected boundaries are
+ * exchanged at every Runge-Kutta stage).  CFD_GHOSTS_DIRECT (default): every
+ * receiver ghost is copied straight from the donor's interior in the same
+ * launch as the physical patches (all blocks are on this GPU; Sec. 5 fills
+ * self-connected ghosts by copying).  CFD_GHOSTS_PACKED: the donor strips are
+ * packed into per-connection segments of the exchange buffer, then unpacked
+ * into the receivers (Sec. 7.2 V1/V5), the form a transfer between GPUs would
+ * take.  Bit-identical results.  CFD_ERR_ARG for another mode. */
+cfd_status cfd_set_ghost_exchange(cfd_ctx* ctx, int mode);
 
 /* Time every compiled tile shape of the stage kernel on the bound problem
  * (reps launches each) and keep the fastest.  *chosen (may be NULL) receives

@@ -17,7 +17,8 @@ FLUX = {"roe": 0, "vanleer_fvs": 1, "steger_warming": 2}
 BC = {"slip_wall": 1, "sup_inflow": 2, "extrap_outflow": 3, "farfield": 4, "sub_inflow": 5, "sub_outflow": 6,
       "noslip_wall": 7}
 DT_CFL, DT_FIXED, DT_LOCAL = 0, 1, 2
-EXEC_BATCHED, EXEC_PER_BLOCK = 0, 1
+EXEC_BATCHED, EXEC_PER_BLOCK, EXEC_PERSISTENT = 0, 1, 2
+GHOSTS_DIRECT, GHOSTS_PACKED = 0, 1
 CHECK_FINITE, NAN_GHOSTS = 1, 2  # cfd_config.debug_flags
 Q = {"nblocks": 0, "ncells": 1, "nvar": 2, "nvariants": 3, "variant": 4, "ntiles": 5, "ntransfers": 6,
      "npatches": 7, "nnodes": 8, "exchange_doubles": 9, "workspace_bytes": 10, "tile_x": 11, "tile_y": 12}
@@ -66,6 +67,7 @@ SIGNATURES = {
     "cfd_padded_primitives": ([_P, _P], _I),
     "cfd_padded_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], _I),
     "cfd_set_exec": ([_P, _I, _I], _I),
+    "cfd_set_ghost_exchange": ([_P, _I], _I),
     "cfd_autotune": ([_P, _I, _IA], _I),
     "cfd_set_variant": ([_P, _I], _I),
     "cfd_profile": ([_P, _I], _I),

@@ -65,6 +65,8 @@ struct cfd_ctx {
   std::vector<PatchDev> patches;
   std::vector<ChunkDev> chunks1, chunks2;     // phase 1 (pack + patches) and 2 (unpack), block-sorted
   std::vector<int> c1_begin, c2_begin;        // per-block chunk ranges (size nblocks + 1)
+  std::vector<ChunkDev> chunksd;              // direct exchange: copies + patches, sorted by receiving block
+  std::vector<int> cd_begin;                  // per-block ranges of chunksd (size nblocks + 1)
   int nvariants = 0;
   std::vector<std::vector<TileDev>> tiles_batched, tiles_block;  // per variant
   std::vector<std::vector<int>> tile_begin;                      // per variant, per block (+1)
@@ -82,13 +84,14 @@ struct cfd_ctx {
   size_t ws_bytes = 0;
   size_t off_stA = 0, off_stB = 0, off_stC = 0, off_metric = 0, off_nodes = 0, off_xbuf = 0, off_inflow = 0,
          off_dt = 0, off_dtmin = 0, off_err = 0, off_blocks = 0, off_xfers = 0, off_patches = 0, off_chunks1 = 0,
-         off_chunks2 = 0, off_export = 0;
+         off_chunks2 = 0, off_chunksd = 0, off_export = 0;
   std::vector<size_t> off_tiles_batched, off_tiles_block;
 
   // execution
   int variant = 0;
   int exec_mode = CFD_EXEC_BATCHED;
   int use_graph = 1;
+  int ghost_mode = CFD_GHOSTS_DIRECT;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   bool graph_valid = false;
@@ -584,6 +587,18 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   }
   c->c1_begin[nb] = (int)c->chunks1.size();
   c->c2_begin[nb] = (int)c->chunks2.size();
+  // direct exchange: every connected ghost copied from the donor interior and
+  // every physical patch, in one launch (per receiving block in per-block mode)
+  c->chunksd.clear();
+  c->cd_begin.assign(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) {
+    c->cd_begin[b] = (int)c->chunksd.size();
+    for (size_t x = 0; x < c->xfers.size(); ++x)
+      if (c->xfers[x].rblock == b) add_chunks(c->chunksd, 3, (int)x, NG * c->xfers[x].len0 * c->xfers[x].len1);
+    for (size_t p = 0; p < c->patches.size(); ++p)
+      if (c->patches[p].block == b) add_chunks(c->chunksd, 1, (int)p, NG * c->patches[p].len0 * c->patches[p].len1);
+  }
+  c->cd_begin[nb] = (int)c->chunksd.size();
 
   // --- tiles per variant -------------------------------------------------------
   int nvar_t = 0;
@@ -655,6 +670,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->off_patches = take(c->patches.size() * sizeof(PatchDev));
   c->off_chunks1 = take(c->chunks1.size() * sizeof(ChunkDev));
   c->off_chunks2 = take(c->chunks2.size() * sizeof(ChunkDev));
+  c->off_chunksd = take(c->chunksd.size() * sizeof(ChunkDev));
   c->off_export = take(c->export_off.size() * sizeof(long long));
   c->off_tiles_batched.assign(nvar_t, 0);
   c->off_tiles_block.assign(nvar_t, 0);
@@ -826,6 +842,7 @@ extern "C" cfd_status cfd_bind_workspace(cfd_ctx* c, void* ptr, size_t bytes) {
   if ((s = upload(c, c->off_patches, c->patches)) != CFD_OK) return s;
   if ((s = upload(c, c->off_chunks1, c->chunks1)) != CFD_OK) return s;
   if ((s = upload(c, c->off_chunks2, c->chunks2)) != CFD_OK) return s;
+  if ((s = upload(c, c->off_chunksd, c->chunksd)) != CFD_OK) return s;
   if ((s = upload(c, c->off_export, c->export_off)) != CFD_OK) return s;
   for (int v = 0; v < c->nvariants; ++v) {
     if ((s = upload(c, c->off_tiles_batched[v], c->tiles_batched[v])) != CFD_OK) return s;
@@ -956,6 +973,19 @@ static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s) {
     n.dst = q;
     HIP_TRY(c, launch_nan_ghosts(c->dim, n, c->max_padded, nb, s));
   }
+  if (c->ghost_mode == CFD_GHOSTS_DIRECT) {
+    g.chunks = c->dptr<ChunkDev>(c->off_chunksd);
+    if (c->exec_mode == CFD_EXEC_PER_BLOCK) {
+      for (int b = 0; b < nb; ++b) {
+        g.chunk_begin = c->cd_begin[b];
+        HIP_TRY(c, launch_ghost(c->dim, g, c->cd_begin[b + 1] - c->cd_begin[b], s));
+      }
+    } else {
+      g.chunk_begin = 0;
+      HIP_TRY(c, launch_ghost(c->dim, g, (int)c->chunksd.size(), s));
+    }
+    return CFD_OK;
+  }
   if (c->exec_mode == CFD_EXEC_PER_BLOCK) {
     g.chunks = c->dptr<ChunkDev>(c->off_chunks1);
     for (int b = 0; b < nb; ++b) {
@@ -1000,13 +1030,15 @@ static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool 
     for (int b = 0; b < nb; ++b) {
       a.tile_begin = c->tile_begin[v][b];
       a.tile_end = c->tile_begin[v][b + 1];
-      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->frozen ? LIM_FROZEN : c->cfg.limiter, v, c->has_farfield, a, a.tile_end - a.tile_begin, s));
+      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->frozen ? LIM_FROZEN : c->cfg.limiter, v, c->has_farfield, a,
+                              a.tile_end - a.tile_begin, false, s));
     }
   } else {
     a.tiles = c->dptr<TileDev>(c->off_tiles_batched[v]);
     a.tile_begin = 0;
     a.tile_end = (int)c->tiles_batched[v].size();
-    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->frozen ? LIM_FROZEN : c->cfg.limiter, v, c->has_farfield, a, a.tile_end, s));
+    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->frozen ? LIM_FROZEN : c->cfg.limiter, v, c->has_farfield, a,
+                            a.tile_end, c->exec_mode == CFD_EXEC_PERSISTENT, s));
   }
   if (timed) {
     HIP_TRY(c, hipEventRecord(ev->b, s));
@@ -1184,7 +1216,7 @@ extern "C" cfd_status cfd_rk_step(cfd_ctx* c, int nsteps, double* dev_dt_last) {
   if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
   if ((s = ensure_dt(c)) != CFD_OK) return s;
   const bool check = c->cfg.debug_flags & CFD_CHECK_FINITE;
-  const bool graph = c->use_graph && c->exec_mode == CFD_EXEC_BATCHED && !c->profiling && !c->cfg.debug_flags;
+  const bool graph = c->use_graph && c->exec_mode != CFD_EXEC_PER_BLOCK && !c->profiling && !c->cfg.debug_flags;
   if (graph && !c->graph_valid && nsteps > 0)
     if ((s = build_graph(c)) != CFD_OK) return s;
   for (int n = 0; n < nsteps; ++n) {
@@ -1231,9 +1263,18 @@ extern "C" cfd_status cfd_padded_primitives(cfd_ctx* c, double* dev_out) {
 
 extern "C" cfd_status cfd_set_exec(cfd_ctx* c, int mode, int use_graph) {
   if (!c) return CFD_ERR_ARG;
-  if (mode != CFD_EXEC_BATCHED && mode != CFD_EXEC_PER_BLOCK) return fail(c, CFD_ERR_ARG, "bad exec mode");
+  if (mode != CFD_EXEC_BATCHED && mode != CFD_EXEC_PER_BLOCK && mode != CFD_EXEC_PERSISTENT)
+    return fail(c, CFD_ERR_ARG, "bad exec mode");
   c->exec_mode = mode;
   c->use_graph = use_graph ? 1 : 0;
+  release_graph(c);
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_set_ghost_exchange(cfd_ctx* c, int mode) {
+  if (!c) return CFD_ERR_ARG;
+  if (mode != CFD_GHOSTS_DIRECT && mode != CFD_GHOSTS_PACKED) return fail(c, CFD_ERR_ARG, "bad ghost exchange mode");
+  c->ghost_mode = mode;
   release_graph(c);
   return CFD_OK;
 }

@@ -75,7 +75,8 @@ struct PatchDev {
 };
 
 // A work chunk of a ghost-fill launch: CHUNK consecutive elements of one item.
-// kind 0: pack a transfer; 1: fill a physical patch; 2: unpack a transfer.
+// kind 0: pack a transfer; 1: fill a physical patch; 2: unpack a transfer;
+// 3: copy a transfer from donor interior to receiver ghosts directly.
 struct ChunkDev {
   int kind, item, start, count;
 };

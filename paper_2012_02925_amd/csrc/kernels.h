@@ -52,9 +52,11 @@ struct StageVariant {
 const StageVariant* stage_variants(int dim, int* count);
 hipError_t launch_sumsq(int nvar, const double* R, long long ncells, double* partial, int nparts,
                         double* norms, hipStream_t s);
-// ff: some block has a farfield patch (selects the kernels that test for it)
+// ff: some block has a farfield patch (selects the kernels that test for it);
+// persistent: cap the grid at the workgroups the device holds at once (the
+// kernel's grid-stride loop then walks the rest of the tile list)
 hipError_t launch_stage(int dim, int flux, int lim, int variant, bool ff, const StageArgs& a, int grid,
-                        hipStream_t s);
+                        bool persistent, hipStream_t s);
 hipError_t launch_ghost(int dim, const GhostArgs& a, int nchunks, hipStream_t s);
 hipError_t launch_set_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
 hipError_t launch_get_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);

@@ -13,7 +13,10 @@ namespace cfd {
 
 // ---------------------------------------------------------------------------
 // ghost fill: pack / physical patches / unpack (Sec. 2 ghost cells; Sec. 7.2
-// V1 pack/unpack and V5 persistent per-connection buffers)
+// V1 pack/unpack and V5 persistent per-connection buffers), or, for blocks
+// on the same GPU, connected ghosts filled directly by copying the donor's
+// interior (Sec. 5: self-connected ghosts are filled by copying) in the same
+// launch as the physical patches
 
 template <int DIM>
 __device__ __forceinline__ void mirror_velocity(double* q, const double* S) {
@@ -107,6 +110,30 @@ __global__ void __launch_bounds__(CHUNK) ghost_kernel(GhostArgs a) {
   const ChunkDev ch = a.chunks[a.chunk_begin + blockIdx.x];
   const int e = ch.start + threadIdx.x;
   if (threadIdx.x >= ch.count) return;
+  if (ch.kind == 3) {
+    // direct copy of a connection (same GPU): the donor's interior layer
+    // `layer` at the mapped position straight into the receiver's ghost
+    // layer, the composition of the pack and unpack below without the buffer
+    const TransferDev x = a.xfers[ch.item];
+    const int layer = e & 1;
+    const int r = e >> 1;
+    const int r1 = r % x.len0, r2 = r / x.len0;
+    int d1, d2;
+    orient_map(x.orient, r1, r2, x.dlen0, x.dlen1, d1, d2);
+    const BlockDev& D = a.blocks[x.dblock];
+    const BlockDev& R = a.blocks[x.rblock];
+    int i, j, k, gi, gj, gk;
+    face_cell(D, DIM, x.dface, layer, false, x.dlo0 + d1, x.dlo1 + d2, i, j, k);
+    face_cell(R, DIM, x.rface, layer, true, x.rlo0 + r1, x.rlo1 + r2, gi, gj, gk);
+    const double* qd = a.q + D.origin + pidx(D, i, j, k);
+    double* qr = a.q + R.origin + pidx(R, gi, gj, gk);
+    double val[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) val[v] = qd[v * D.vstride];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) qr[v * R.vstride] = val[v];
+    return;
+  }
   if (ch.kind == 0 || ch.kind == 2) {
     const TransferDev x = a.xfers[ch.item];
     const int per_layer = x.len0 * x.len1;
@@ -505,8 +532,9 @@ const StageVariant* stage_variants(int dim, int* count) {
 }
 
 hipError_t launch_stage(int dim, int flux, int lim, int variant, bool ff, const StageArgs& a, int grid,
-                        hipStream_t s) {
-  return dim == 2 ? launch_stage_2d(flux, lim, variant, ff, a, grid, s) : launch_stage_3d(flux, lim, variant, ff, a, grid, s);
+                        bool persistent, hipStream_t s) {
+  return dim == 2 ? launch_stage_2d(flux, lim, variant, ff, a, grid, persistent, s)
+                  : launch_stage_3d(flux, lim, variant, ff, a, grid, persistent, s);
 }
 
 // ---------------------------------------------------------------------------

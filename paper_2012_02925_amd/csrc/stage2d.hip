@@ -3,11 +3,12 @@
 
 namespace cfd {
 
-hipError_t launch_stage_2d(int flux, int lim, int variant, bool ff, const StageArgs& a, int grid, hipStream_t s) {
+hipError_t launch_stage_2d(int flux, int lim, int variant, bool ff, const StageArgs& a, int grid, bool pers,
+                           hipStream_t s) {
   switch (variant) {
-    case 0: return launch_stage_flux<2, 64, 4, 1>(flux, lim, ff, a, grid, s);
-    case 1: return launch_stage_flux<2, 32, 8, 1>(flux, lim, ff, a, grid, s);
-    default: return launch_stage_flux<2, 16, 16, 1>(flux, lim, ff, a, grid, s);
+    case 0: return launch_stage_flux<2, 64, 4, 1>(flux, lim, ff, a, grid, pers, s);
+    case 1: return launch_stage_flux<2, 32, 8, 1>(flux, lim, ff, a, grid, pers, s);
+    default: return launch_stage_flux<2, 16, 16, 1>(flux, lim, ff, a, grid, pers, s);
   }
 }
 

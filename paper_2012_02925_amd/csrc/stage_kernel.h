@@ -273,6 +273,8 @@ stage_kernel(StageArgs a) {
     // the own cell waits in LDS (only its own thread touches that slot).
     // Inside a plane q(k) is read back from LDS, so qc is dead there.
     double qc[NV], qn[NV], qnx[NV], scp[NV], scm[NS == 2 ? NV : 1], fzd[NV];
+    // (DT, 3D) area vector of the own cell's low k-face: the previous plane's Sz
+    double szlo[DT && DIM == 3 ? 3 : 1];
     double pprev = 0.0;
     // slopes of cell k+1 from q(k), q(k+1), q(k+2); flux of face k+1; shift the queue
     auto zstep = [&](int k, const double* qcur, const double* qnn, const double* Sz, double* F) {
@@ -332,6 +334,10 @@ stage_kernel(StageArgs a) {
         for (int v = 0; v < NV; ++v) q2[v] = ld_at(qin + v * vs, zoff(kbeg + 1));
 #pragma unroll
         for (int c = 0; c < 3; ++c) Sz[c] = ld_at(met + ML::S(2, c) * vs, zoff(kbeg));
+        if constexpr (DT) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) szlo[c] = Sz[c];
+        }
         zstep(kbeg - 1, qc, q2, Sz, fzd);
 #pragma unroll
         for (int v = 0; v < NV; ++v) fzs[v][tid] = fzd[v];
@@ -591,18 +597,18 @@ stage_kernel(StageArgs a) {
       __syncthreads();
 
       // ---- 4. divergence and update ---------------------------------------
-      // (DT) mean area vectors Sbar_d of the cell, all loads issued at once
-      // ahead of the divergence (issued one pair at a time, their latency
-      // was exposed in turn)
+      // (DT) mean area vectors Sbar_d of the cell, ahead of the divergence:
+      // the own low i- and j-faces (Sx, Sy) and both k-faces (szlo, Sz) are
+      // still in registers, only the high i- and j-faces are loaded
       double sbar[DT ? DIM : 1][DIM];
       if constexpr (DT) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          const unsigned step = d == 0 ? 8u : (d == 1 ? 8u * B.pi : p8);
-#pragma unroll
-          for (int cc = 0; cc < DIM; ++cc) {
-            const double* md = met + ML::S(d, cc) * vs;
-            sbar[d][cc] = 0.5 * (ld_at(md, ok) + ld_at(md, ok + step));
+        for (int cc = 0; cc < DIM; ++cc) {
+          sbar[0][cc] = 0.5 * (Sx[cc] + ld_at(met + ML::S(0, cc) * vs, ok + 8u));
+          sbar[1][cc] = 0.5 * (Sy[cc] + ld_at(met + ML::S(1, cc) * vs, ok + 8u * B.pi));
+          if constexpr (DIM == 3) {
+            sbar[2][cc] = 0.5 * (szlo[cc] + Sz[cc]);
+            szlo[cc] = Sz[cc];
           }
         }
       }

@@ -197,8 +197,13 @@ class Solver:
         self._check(self.lib.cfd_set_bc_params(self.ctx, patch_id, ctypes.cast(arr, capi._DP)))
 
     def set_exec(self, mode="batched", use_graph=True):
-        m = capi.EXEC_BATCHED if mode == "batched" else capi.EXEC_PER_BLOCK
+        m = {"batched": capi.EXEC_BATCHED, "per_block": capi.EXEC_PER_BLOCK,
+             "persistent": capi.EXEC_PERSISTENT}[mode]
         self._check(self.lib.cfd_set_exec(self.ctx, m, 1 if use_graph else 0))
+
+    def set_ghost_exchange(self, mode="direct"):
+        m = {"direct": capi.GHOSTS_DIRECT, "packed": capi.GHOSTS_PACKED}[mode]
+        self._check(self.lib.cfd_set_ghost_exchange(self.ctx, m))
 
     def set_variant(self, v):
         self._check(self.lib.cfd_set_variant(self.ctx, int(v)))
