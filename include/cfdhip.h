@@ -226,6 +226,19 @@ cfd_status cfd_residual(cfd_ctx* ctx, double* dev_R);
  * partition of the cells and fixed reduction order. */
 cfd_status cfd_residual_norms(cfd_ctx* ctx, double* dev_R, double* dev_norms);
 
+/* cfd_residual_norms for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments and results, but the per-part partial sums
+ * live in a library-owned static device array (40 KiB per GPU, held until the
+ * process ends) instead of the context workspace, and the call allocates
+ * nothing.  Every call on one GPU shares that array: calls that overlap in
+ * time on one GPU (different streams or threads) race and must be
+ * serialised by the caller.  CFD_ERR_UNSUPPORTED if the partial sums would
+ * exceed the array (1024 parts x 5 variables; not reachable with the fixed
+ * partition), CFD_ERR_HIP if the array has no address on the context's
+ * device. */
+cfd_status cfd_residual_norms_noalloc(cfd_ctx* ctx, double* dev_R, double* dev_norms);
+
 /* Limiter freezing for steady runs (Sec. 8.2, the laminar NACA 0012 case: the limiter is frozen late in a
  * steady run so the residual keeps falling; no formula is printed).  Reading:
  * per cell, direction and primitive variable the factor

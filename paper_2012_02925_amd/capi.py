@@ -78,6 +78,7 @@ SIGNATURES = {
     "cfd_adjoint_reset": ([_P], _I),
     "cfd_rk_step_vjp": ([_P, _P], _I),
     "cfd_residual_norms": ([_P, _P, _P], _I),
+    "cfd_residual_norms_noalloc": ([_P, _P, _P], _I),
     "cfd_enable_limiter_freezing": ([_P, _I], _I),
     "cfd_freeze_limiter": ([_P, _I], _I),
     "cfd_rk_step_record": ([_P, _P], _I),

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -209,6 +210,34 @@ cfd_status need(cfd_ctx* c, bool finalized, bool bound) {
 
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Library-owned scratch for the entry point that allocates nothing
+// (cfd_residual_norms_noalloc): the per-part partial sums of the residual
+// norms.  One copy per GPU, alive until the process ends; its device address
+// is looked up once per device (at cfd_create, with that device current) and
+// only that address is passed to kernels.
+constexpr int SCRATCH_DOUBLES = 1024 * 5;  // parts x variables, 40 KiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+static hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return e;
+}
+
+static double* scratch_of(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 extern "C" const char* cfd_version(void) { return "cfdhip 0.1 (gfx950, fp64)"; }
 
 extern "C" const char* cfd_status_string(cfd_status s) {
@@ -254,6 +283,9 @@ extern "C" cfd_status cfd_create(const cfd_config* cfg, void* stream, cfd_ctx** 
   // Without a usable device the context still plans (add/set/connect/finalize);
   // binding a workspace then fails with CFD_ERR_HIP.
   if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
+  // the no-allocation entry point's scratch: its address on this device
+  // (failure is reported by that entry point, which cannot run without it)
+  if (c->device >= 0) (void)scratch_setup(c->device);
   int n = 0;
   stage_variants(c->dim, &n);
   c->nvariants = n;
@@ -1191,6 +1223,22 @@ extern "C" cfd_status cfd_residual_norms(cfd_ctx* c, double* dev_R, double* dev_
   if (s != CFD_OK) return s;
   const int parts = (int)std::min<long long>(cfd_ctx::NORM_PARTS, std::max<long long>(1, c->ncells / 4096));
   HIP_TRY(c, launch_sumsq(c->nvar, dev_R, c->ncells, c->dptr<double>(c->off_normpart), parts, dev_norms, c->stream));
+  return CFD_OK;
+}
+
+extern "C" cfd_status cfd_residual_norms_noalloc(cfd_ctx* c, double* dev_R, double* dev_norms) {
+  if (!dev_norms || !dev_R) return CFD_ERR_ARG;
+  cfd_status s = need(c, true, true);
+  if (s != CFD_OK) return s;
+  double* part = scratch_of(c->device);
+  if (!part) return fail(c, CFD_ERR_HIP, "the library scratch has no device address on device %d", c->device);
+  const int parts = (int)std::min<long long>(cfd_ctx::NORM_PARTS, std::max<long long>(1, c->ncells / 4096));
+  if ((long long)parts * c->nvar > SCRATCH_DOUBLES)
+    return fail(c, CFD_ERR_UNSUPPORTED, "%d partial sums exceed the library scratch of %d doubles", parts * c->nvar,
+                SCRATCH_DOUBLES);
+  if ((s = cfd_residual(c, dev_R)) != CFD_OK) return s;
+  // every partial slot [v][part] is written before it is read: nothing to clear
+  HIP_TRY(c, launch_sumsq(c->nvar, dev_R, c->ncells, part, parts, dev_norms, c->stream));
   return CFD_OK;
 }
 
