@@ -12,7 +12,9 @@ compare those cells at the 1e-10 state bar.
   fullsize_box_256.json     3D jittered periodic box 256^3, van Albada, Roe,
                             RK4, CFL 0.5: samples after 50 steps
 
-usage: python tests/golden/make_fullsize_samples.py [ramp|box ...]
+usage: python tests/golden/make_fullsize_samples.py [--resume DIR] [ramp|box ...]
+(--resume DIR keeps the oracle's state there every 5 steps and continues an
+interrupted run from it)
 """
 import json
 import os
@@ -38,21 +40,32 @@ def sample_cells(case, seed):
     return np.sort(cells)
 
 
-def run(case, snapshots, cells, out_path, meta):
+def run(case, snapshots, cells, out_path, meta, resume_dir=None, every=5):
+    """resume_dir: where to keep the oracle's state every `every` steps, so an
+    interrupted run continues from its last saved step (optional)."""
     torch.set_default_dtype(torch.float64)
     P = oracle.Problem(case)
     met = P.metrics()
     Q = P.initial_state()
-    dts, snaps = [], {}
+    dts, snaps, start = [], {}, 0
+    ck = os.path.join(resume_dir, case.name + ".pt") if resume_dir else None
+    if ck and os.path.exists(ck):
+        saved = torch.load(ck, weights_only=True)
+        Q, dts, start = list(saved["Q"]), list(saved["dt"]), int(saved["step"])
+        snaps = json.loads(saved["snaps"])
+        print("%s resumed at step %d" % (case.name, start), flush=True)
     idx = torch.tensor(cells, dtype=torch.long)
     t0 = time.time()
-    for n in range(1, max(snapshots) + 1):
+    for n in range(start + 1, max(snapshots) + 1):
         Q, dt = P.rk_step(Q, met)
         dts.append(float(dt))
         if n in snapshots:
             flat = torch.cat([q.reshape(case.nvar, -1) for q in Q], dim=1)
             snaps[str(n)] = flat[:, idx].tolist()
         print("%s step %d dt %.17g (%.0f s)" % (case.name, n, float(dt), time.time() - t0), flush=True)
+        if ck and n % every == 0:
+            torch.save({"Q": [q.detach() for q in Q], "dt": dts, "step": n, "snaps": json.dumps(snaps)}, ck + ".tmp")
+            os.replace(ck + ".tmp", ck)
     doc = dict(meta)
     doc.update({"workload": case.name, "cells": [int(c) for c in cells], "dt": dts, "state": snaps,
                 "layout": "packed conservative [var][cell], cells in k-j-i order (i fastest)",
@@ -62,20 +75,25 @@ def run(case, snapshots, cells, out_path, meta):
     print("wrote", out_path, flush=True)
 
 
-def ramp():
+def ramp(resume_dir=None):
     case = synth.compression_ramp(1024, 1024)
     cells = np.union1d(sample_cells(case, 101), np.arange(0, 1024, 4))  # + every 4th wall-row cell
     run(case, [100, 500], cells, os.path.join(HERE, "fullsize_ramp_1024.json"),
-        {"steps": 500, "generator": "synth.compression_ramp(1024, 1024)"})
+        {"steps": 500, "generator": "synth.compression_ramp(1024, 1024)"}, resume_dir)
 
 
-def box():
+def box(resume_dir=None):
     case = synth.jittered_periodic_box(n=256, seed=0)
     run(case, [50], sample_cells(case, 202), os.path.join(HERE, "fullsize_box_256.json"),
-        {"steps": 50, "generator": "synth.jittered_periodic_box(n=256, seed=0)"})
+        {"steps": 50, "generator": "synth.jittered_periodic_box(n=256, seed=0)"}, resume_dir)
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["ramp", "box"]
-    for w in which:
-        {"ramp": ramp, "box": box}[w]()
+    args = sys.argv[1:]
+    resume = None
+    if args[:1] == ["--resume"]:
+        resume = args[1]
+        os.makedirs(resume, exist_ok=True)
+        args = args[2:]
+    for w in args or ["ramp", "box"]:
+        {"ramp": ramp, "box": box}[w](resume)
