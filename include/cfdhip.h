@@ -318,7 +318,9 @@ cfd_status cfd_kernel_time(cfd_ctx* ctx, double* total_ms, long long* launches);
  * before cfd_finalize (it reserves the extra workspace).  Cotangents use the
  * same layouts as their primal values (packed conservative state, node
  * layout, dim+2 values per inflow patch in patch-id order of the inflow
- * patches).  Node gradients are implemented for 2D grids. */
+ * patches).  Node gradients cover 2D and 3D grids (2D: the face vectors and
+ * diagonal-product areas; 3D: the half cross products of face diagonals and
+ * the mean-node face sums of the cell volumes, transposed per node). */
 
 /* Reserve adjoint workspace (call before cfd_finalize). */
 cfd_status cfd_enable_adjoint(cfd_ctx* ctx, int enable);
@@ -349,7 +351,7 @@ cfd_status cfd_rk_step_vjp_recorded(cfd_ctx* ctx, const void* dev_stages, double
 /* J = sum over slip-wall faces of p_w |S| (integrated wall pressure) into
  * dev_J[0]; dev_Qbar (nullable) = dJ/dQ; dJ/dS accumulates. */
 cfd_status cfd_objective_wall_pressure(cfd_ctx* ctx, double* dev_J, double* dev_Qbar);
-/* Node gradient (2D) and inflow-state gradient of everything accumulated since
+/* Node gradient and inflow-state gradient of everything accumulated since
  * the last reset (both nullable). */
 cfd_status cfd_adjoint_result(cfd_ctx* ctx, double* dev_Xbar, double* dev_BCbar);
 /* dev_thetabar[dim+2] = (dQ/dtheta)^T sum over cells of dev_Qbar, for a

@@ -49,7 +49,7 @@ hipError_t launch_vjp_inflow_reduce(int dim, const VjpArgs& a, hipStream_t s);
 hipError_t launch_vjp_finalize(int dim, const VjpArgs& a, long long max_cells, int nb, hipStream_t s);
 hipError_t launch_objective(int dim, const VjpArgs& a, const ChunkDev* chunks, int begin, int count, hipStream_t s);
 hipError_t launch_objective_sum(const VjpArgs& a, const int* wall_patches, int nwall, double* J, hipStream_t s);
-hipError_t launch_node_vjp_2d(const VjpArgs& a, double* Xb, long long max_nodes, int nb, hipStream_t s);
+hipError_t launch_node_vjp(int dim, const VjpArgs& a, double* Xb, long long max_nodes, int nb, hipStream_t s);
 hipError_t launch_uniform_state_vjp(int dim, const double* Qbar, long long ncells, double* partial, int nparts,
                                     double* thetabar, Gas g, const double* theta, hipStream_t s);
 

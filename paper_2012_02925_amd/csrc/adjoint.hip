@@ -1081,6 +1081,88 @@ __global__ void node_vjp_2d_kernel(VjpArgs a, double* Xb) {
 }
 
 // ---------------------------------------------------------------------------
+// node gradient (3D): gather dJ/dS and dJ/dOmega onto the nodes
+//
+// A face with nodes a b c d has S = 1/2 (c - a) x (d - b) and mean node
+// m = (a + b + c + d) / 4; a cell volume is 1/3 of the sum over its faces of
+// m . S with outward sign, so face f along an axis (high face of cell f-1, low
+// face of cell f) passes w = (Ob(f-1) - Ob(f)) / 3 to d(m . S).  With
+// St = Sb + w m, u = c - a and v = d - b:  ubar = 1/2 v x St and
+// vbar = 1/2 St x u; a takes -ubar, c +ubar, b -vbar, d +vbar, and each of
+// the four nodes w S / 4.  One thread per node gathers its (up to) twelve faces.
+
+__device__ __forceinline__ void cross3v(const double* x, const double* y, double* z) {
+  z[0] = x[1] * y[2] - x[2] * y[1];
+  z[1] = x[2] * y[0] - x[0] * y[2];
+  z[2] = x[0] * y[1] - x[1] * y[0];
+}
+
+__global__ void __launch_bounds__(256) node_vjp_3d_kernel(VjpArgs a, double* Xb) {
+  using ML = MetricLayout<3>;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const int ni1 = B.ni + 1, nj1 = B.nj + 1, nk1 = B.nk + 1;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long long)ni1 * nj1 * nk1) return;
+  const int node[3] = {(int)(c % ni1), (int)((c / ni1) % nj1), (int)(c / ((long long)ni1 * nj1))};
+  const int n[3] = {B.ni, B.nj, B.nk};
+  const long long vs = B.vstride, nn = B.nnode_total;
+  const double* mb = a.metricbar + B.morigin;
+  // corner offsets of a, b, c, d per face axis (the node order of the forward metrics)
+  constexpr int OFF[3][4][3] = {{{0, 0, 0}, {0, 1, 0}, {0, 1, 1}, {0, 0, 1}},
+                                {{0, 0, 0}, {0, 0, 1}, {1, 0, 1}, {1, 0, 0}},
+                                {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0}}};
+  double xb[3] = {0.0, 0.0, 0.0};
+  for (int ax = 0; ax < 3; ++ax) {
+    for (int r = 0; r < 4; ++r) {
+      int f[3];
+      bool ok = true;
+      for (int d = 0; d < 3; ++d) {
+        f[d] = node[d] - OFF[ax][r][d];
+        if (d != ax && (f[d] < 0 || f[d] >= n[d])) ok = false;
+      }
+      if (!ok) continue;
+      double p[4][3];
+      for (int q = 0; q < 4; ++q) {
+        const long long o =
+            B.node0 + ((long long)(f[2] + OFF[ax][q][2]) * nj1 + f[1] + OFF[ax][q][1]) * ni1 + f[0] + OFF[ax][q][0];
+        for (int cc = 0; cc < 3; ++cc) p[q][cc] = a.nodes[cc * nn + o];
+      }
+      double u[3], v[3], m[3], S[3], St[3];
+      for (int cc = 0; cc < 3; ++cc) {
+        u[cc] = p[2][cc] - p[0][cc];
+        v[cc] = p[3][cc] - p[1][cc];
+        m[cc] = 0.25 * (p[0][cc] + p[1][cc] + p[2][cc] + p[3][cc]);
+      }
+      cross3v(u, v, S);
+      for (int cc = 0; cc < 3; ++cc) S[cc] *= 0.5;
+      // w = (Ob(f-1) - Ob(f)) / 3 along the face axis; cells outside the block give 0
+      double w = 0.0;
+      if (f[ax] > 0) {
+        int g[3] = {f[0], f[1], f[2]};
+        g[ax] -= 1;
+        w += mb[ML::INVVOL * vs + pidx(B, g[0], g[1], g[2])];
+      }
+      if (f[ax] < n[ax]) w -= mb[ML::INVVOL * vs + pidx(B, f[0], f[1], f[2])];
+      w *= (1.0 / 3.0);
+      const long long fidx = pidx(B, f[0], f[1], f[2]);
+      for (int cc = 0; cc < 3; ++cc) St[cc] = mb[ML::S(ax, cc) * vs + fidx] + w * m[cc];
+      double g[3];
+      if (r == 0 || r == 2) {
+        cross3v(v, St, g);  // 2 ubar
+        const double sg = r == 0 ? -0.5 : 0.5;
+        for (int cc = 0; cc < 3; ++cc) xb[cc] += sg * g[cc];
+      } else {
+        cross3v(St, u, g);  // 2 vbar
+        const double sg = r == 1 ? -0.5 : 0.5;
+        for (int cc = 0; cc < 3; ++cc) xb[cc] += sg * g[cc];
+      }
+      for (int cc = 0; cc < 3; ++cc) xb[cc] += 0.25 * w * S[cc];
+    }
+  }
+  for (int cc = 0; cc < 3; ++cc) Xb[cc * nn + B.node0 + c] = xb[cc];
+}
+
+// ---------------------------------------------------------------------------
 // cell sums (deterministic two-level reduction) and the uniform-state VJP
 
 template <int DIM>
@@ -1224,8 +1306,11 @@ hipError_t launch_objective_sum(const VjpArgs& a, const int* wall_patches, int n
   return hipGetLastError();
 }
 
-hipError_t launch_node_vjp_2d(const VjpArgs& a, double* Xb, long long max_nodes, int nb, hipStream_t s) {
-  hipLaunchKernelGGL(node_vjp_2d_kernel, grid2(max_nodes, nb), dim3(256), 0, s, a, Xb);
+hipError_t launch_node_vjp(int dim, const VjpArgs& a, double* Xb, long long max_nodes, int nb, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(node_vjp_2d_kernel, grid2(max_nodes, nb), dim3(256), 0, s, a, Xb);
+  else
+    hipLaunchKernelGGL(node_vjp_3d_kernel, grid2(max_nodes, nb), dim3(256), 0, s, a, Xb);
   return hipGetLastError();
 }
 

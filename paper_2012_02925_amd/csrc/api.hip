@@ -1545,9 +1545,8 @@ static cfd_status copy_thetabar(cfd_ctx* c, double* dev_BCbar) {
 
 static cfd_status node_gradient(cfd_ctx* c, double* dev_Xbar) {
   if (!dev_Xbar) return CFD_OK;
-  if (c->dim != 2) return fail(c, CFD_ERR_UNSUPPORTED, "node gradient is implemented for 2D grids");
   VjpArgs a = vjp_args(c, c->stA(), nullptr, 1.0, nullptr, nullptr);
-  HIP_TRY(c, launch_node_vjp_2d(a, dev_Xbar, c->max_nodes, (int)c->blocks.size(), c->stream));
+  HIP_TRY(c, launch_node_vjp(c->dim, a, dev_Xbar, c->max_nodes, (int)c->blocks.size(), c->stream));
   return CFD_OK;
 }
 
@@ -1573,7 +1572,6 @@ extern "C" cfd_status cfd_residual_vjp(cfd_ctx* c, const double* dev_Rbar, doubl
   cfd_status s = need_adjoint(c);
   if (s != CFD_OK) return s;
   if (!dev_Rbar || !dev_Qbar) return CFD_ERR_ARG;
-  if (dev_Xbar && c->dim != 2) return fail(c, CFD_ERR_UNSUPPORTED, "node gradient is implemented for 2D grids");
   if ((s = cfd_adjoint_reset(c)) != CFD_OK) return s;
   if ((s = fill_ghosts(c, c->stA(), c->stream)) != CFD_OK) return s;
   if ((s = vjp_core(c, c->stA(), dev_Rbar, 1.0, dev_Qbar, nullptr)) != CFD_OK) return s;
