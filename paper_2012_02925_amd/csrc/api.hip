@@ -1091,7 +1091,9 @@ static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
   double* Cf = c->stC();
   double* in = A;
   for (int k = 1; k <= M; ++k) {
-    double* out = (k == M) ? A : ((k % 2) ? Bf : Cf);
+    // (a single stage writes into B and is copied back: the kernel reads its
+    // input's neighbours while writing, so it never updates in place)
+    double* out = (k == M && M > 1) ? A : ((k % 2) ? Bf : Cf);
     cfd_status st = stage_prep(c, in, s);
     if (st != CFD_OK) return st;
     StageArgs a = stage_args(c);
@@ -1110,6 +1112,7 @@ static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
     }
     in = out;
   }
+  if (M == 1) HIP_TRY(c, hipMemcpyAsync(A, Bf, (size_t)c->state_doubles * 8, hipMemcpyDeviceToDevice, s));
   return CFD_OK;
 }
 
@@ -1632,7 +1635,8 @@ extern "C" cfd_status cfd_rk_step_record(cfd_ctx* c, void* dev_stages) {
   // Navier-Stokes context, exactly as enqueue_step does
   if ((s = stage_prep(c, A, hs)) != CFD_OK) return s;
   HIP_TRY(c, hipMemcpyAsync(slot0, A, (size_t)c->state_doubles * 8, hipMemcpyDeviceToDevice, hs));
-  const double* in = A;
+  // the first stage reads the copy, so a single stage can write A itself
+  const double* in = slot0;
   for (int k = 1; k <= M; ++k) {
     double* out = (k == M) ? A : slot0 + (size_t)k * c->state_doubles;
     if (k > 1 && (s = stage_prep(c, const_cast<double*>(in), hs)) != CFD_OK) return s;

@@ -165,9 +165,11 @@ def test_residual_vjp_dot_product_with_gpu_fd():
         assert abs(fd - ad) <= 1e-6 * abs(fd)
 
 
-def test_rk_step_vjp_matches_oracle():
-    _say("case: ramp 30x20, one RK step VJP")
+@pytest.mark.parametrize("stages", [1, 2, 4])
+def test_rk_step_vjp_matches_oracle(stages):
+    _say("case: ramp 30x20, one RK step VJP,", stages, "stages")
     case = _ramp(30, 20, dt=2e-3)
+    case.scheme.rk_stages = stages
     s = _solver(case)
     s.set_state(_conservative_from_prims(case).to("cuda:0"))
     rng = np.random.default_rng(5)
@@ -256,11 +258,13 @@ def test_checkpoint_interval_does_not_change_gradient():
         assert torch.equal(g[0], grads[0][0]) and torch.equal(g[1], grads[0][1])
 
 
-def test_recorded_step_matches_recomputed_step():
+@pytest.mark.parametrize("stages", [1, 4])
+def test_recorded_step_matches_recomputed_step(stages):
     """cfd_rk_step_record advances the state like cfd_rk_step, and the VJP over
     its recorded stages equals the VJP that recomputes them, bit for bit."""
-    _say("case: ramp 30x20, recorded vs recomputed step VJP")
+    _say("case: ramp 30x20, recorded vs recomputed step VJP,", stages, "stages")
     case = _ramp(30, 20, dt=2e-3)
+    case.scheme.rk_stages = stages
     s = _solver(case)
     Q0 = _conservative_from_prims(case).to("cuda:0")
     rng = np.random.default_rng(6)

@@ -590,3 +590,24 @@ def test_navier_stokes_steady_machinery():
     rs = torch.as_tensor(residual_scale(case, qr), dtype=torch.float64)
     err = (N.cpu() - Nref).abs()
     assert (err <= 1e-10 * Nref + 1e-11 * rs).all(), (err, Nref)
+
+
+@pytest.mark.parametrize("stages", [1, 2, 3])
+def test_rk_stage_counts_match_oracle(stages):
+    """M-stage schemes other than the classical four (Sec. 2): the state and
+    the time steps of 12 steps against the oracle; M = 1 never updates in
+    place (its stage writes a second buffer that is copied back)."""
+    case = synth.jittered_periodic_box(dims=(20, 18, 16), seed=3)
+    case.scheme.rk_stages = stages
+    case.scheme.cfl = 0.4
+    Qref, dref = oracle_run(case, 12)
+    s = _solver(case)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    dts = []
+    for _ in range(12):
+        s.rk_step(1, dt)
+        dts.append(dt.item())
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    _say("  stages", stages, rep)
+    assert ok, rep
+    assert max(abs(a - b) / b for a, b in zip(dts, dref)) <= 1e-12
