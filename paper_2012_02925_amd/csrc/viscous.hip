@@ -303,16 +303,16 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
       const int ii = i0 - 1 + e % CX, jj = j0 - 1 + e / CX;
       const int out = (ii < 0 || ii >= B.ni) + (jj < 0 || jj >= B.nj) + (kk < 0 || kk >= B.nk);
       pv[h] = e < NC && ii <= B.ni && jj <= B.nj && out <= 1;
-      if (pv[h]) {
-        const long long p = cell_at(ii, jj, kk);
+      // every lane loads (an in-block cell where the item is unused), so no
+      // branch join makes the compiler wait for this prefetch early
+      const long long p = pv[h] ? cell_at(ii, jj, kk) : cell_at(0, 0, min(max(kk, 0), B.nk - 1));
 #pragma unroll
-        for (int x = 0; x < 3; ++x) {
-          pc[h][x] = cen[x * vs + p];
-          pc[h][3 + x] = q[(1 + x) * vs + p];
-        }
-        pc[h][6] = q[p];
-        pc[h][7] = q[4 * vs + p];
+      for (int x = 0; x < 3; ++x) {
+        pc[h][x] = cen[x * vs + p];
+        pc[h][3 + x] = q[(1 + x) * vs + p];
       }
+      pc[h][6] = q[p];
+      pc[h][7] = q[4 * vs + p];
     }
   };
   auto store_cells = [&](int slot) {
@@ -334,6 +334,8 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
       if (e >= NN || I > B.ni || J > B.nj) continue;
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       int cnt = 0;
+      // cells outside the block in two or more directions were staged as
+      // zeros: they add nothing and are not counted
 #pragma unroll
       for (int ai = 0; ai < 2; ++ai)
 #pragma unroll
@@ -341,10 +343,9 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
 #pragma unroll
           for (int ak = 0; ak < 2; ++ak) {
             const int out = (ai == 0 ? I == 0 : I == B.ni) + (aj == 0 ? J == 0 : J == B.nj) + (ak == 0 ? K == 0 : K == B.nk);
-            if (out > 1) continue;
+            cnt += out <= 1;
             const int c = (J - j0 + aj) * CX + (I - i0 + ai);  // cell (I-1+ai, J-1+aj) in the halo frame
             const int sls = ak ? sh : sl;
-            ++cnt;
 #pragma unroll
             for (int w = 0; w < 4; ++w) acc[w] += sc[sls][3 + w][c];
           }
@@ -459,13 +460,16 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     }
     double fzhi[4];
     if (own) zface(k + 1, s0, s1, s1, fzhi);
-    // plane k+2 while the divergence and the next plane's staging run (issued
-    // after the face loops' own loads, which would otherwise wait for it)
-    if (k + 1 < k1) fetch_cells(k + 2);
+    // the cell's inverse volume, then plane k+2 while the divergence and the
+    // next plane's staging run (issued after every load the rest of this
+    // plane waits for, so no wait covers the prefetch)
+    const double ivc = met[ML::INVVOL * vs + cell_at(min(i, B.ni - 1), min(j, B.nj - 1), k)];
+    // (unconditional: after the tile's last plane this reads plane k1 + 1 <=
+    // nk + 1, inside the padded block, and the values go unused)
+    fetch_cells(k + 2);
     __syncthreads();
     if (own) {
-      const long long p = cell_at(i, j, k);
-      const double iv = met[ML::INVVOL * vs + p];
+      const double iv = ivc;
       const long long cell = B.packed + ((long long)k * B.nj + j) * B.ni + i;
       const int ex = ty * NXn + tx, ey = ty * VT_X + tx;
 #pragma unroll
@@ -528,14 +532,15 @@ __global__ void __launch_bounds__(VT2* VT2) viscous_tile2d_kernel(ViscArgs a) {
     if (I > B.ni || J > B.nj) continue;
     double acc[3] = {0.0, 0.0, 0.0};
     int cnt = 0;
+    // corner cells (outside in both directions) were staged as zeros: they
+    // add nothing and are not counted
 #pragma unroll
     for (int ai = 0; ai < 2; ++ai)
 #pragma unroll
       for (int aj = 0; aj < 2; ++aj) {
         const int out = (ai == 0 ? I == 0 : I == B.ni) + (aj == 0 ? J == 0 : J == B.nj);
-        if (out > 1) continue;
+        cnt += out <= 1;
         const int c = (J - j0 + aj) * CX + (I - i0 + ai);
-        ++cnt;
 #pragma unroll
         for (int w = 0; w < 3; ++w) acc[w] += sc[2 + w][c];
       }
