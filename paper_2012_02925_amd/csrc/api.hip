@@ -68,6 +68,9 @@ struct cfd_ctx {
   std::vector<int> c1_begin, c2_begin;        // per-block chunk ranges (size nblocks + 1)
   std::vector<ChunkDev> chunksd;              // direct exchange: copies + patches, sorted by receiving block
   std::vector<int> cd_begin;                  // per-block ranges of chunksd (size nblocks + 1)
+  std::vector<ChunkDev> chunksw;              // chunksd without the connections the stencil reads through
+  std::vector<int> cw_begin;                  // per-block ranges of chunksw
+  bool wrap_any = false;                      // some block axis is periodic onto itself
   int nvariants = 0;
   std::vector<std::vector<TileDev>> tiles_batched, tiles_block;  // per variant
   std::vector<std::vector<int>> tile_begin;                      // per variant, per block (+1)
@@ -85,7 +88,7 @@ struct cfd_ctx {
   size_t ws_bytes = 0;
   size_t off_stA = 0, off_stB = 0, off_stC = 0, off_metric = 0, off_nodes = 0, off_xbuf = 0, off_inflow = 0,
          off_dt = 0, off_dtmin = 0, off_err = 0, off_blocks = 0, off_xfers = 0, off_patches = 0, off_chunks1 = 0,
-         off_chunks2 = 0, off_chunksd = 0, off_export = 0;
+         off_chunks2 = 0, off_chunksd = 0, off_export = 0, off_chunksw = 0;
   std::vector<size_t> off_tiles_batched, off_tiles_block;
 
   // execution
@@ -527,6 +530,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
     const long long nnode = (long long)(h.ni + 1) * (h.nj + 1) * (dim == 3 ? h.nk + 1 : 1);
     node0 += nnode;
     B.wall_mask = 0;
+    B.wrap = 0;
     for (auto& p : c->hpatches)
       if (p.block == b && (p.kind == CFD_BC_SLIP_WALL || p.kind == CFD_BC_NOSLIP_WALL)) B.wall_mask |= 1 << p.face;
       else if (p.block == b && p.kind == CFD_BC_FARFIELD) {
@@ -631,6 +635,37 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
       if (c->patches[p].block == b) add_chunks(c->chunksd, 1, (int)p, NG * c->patches[p].len0 * c->patches[p].len1);
   }
   c->cd_begin[nb] = (int)c->chunksd.size();
+  // Axes along which a block is connected to itself end to end (opposite
+  // faces, full ranges, no reorientation): the stage kernel reads the cells
+  // that those ghosts copy, so the fill between the stages of a step leaves
+  // these connections out (chunksw); every other reader fills in full.
+  c->wrap_any = false;
+  for (auto& h : c->hconns) {
+    if (h.a != h.b || h.fa == h.fb || face_axis(h.fa) != face_axis(h.fb) || h.orient != 0) continue;
+    const int ax = face_axis(h.fa);
+    const HBlock& hb = c->hblocks[h.a];
+    const int t1 = ax == 0 ? hb.nj : hb.ni, t2 = dim == 3 ? (ax == 2 ? hb.nj : hb.nk) : 1;
+    const bool full = h.loa[0] == 0 && h.loa[1] == 0 && h.hia[0] == t1 && h.hia[1] == t2 && h.lob[0] == 0 &&
+                      h.lob[1] == 0 && h.hib[0] == t1 && h.hib[1] == t2;
+    if (!full) continue;
+    c->blocks[h.a].wrap |= 1 << ax;
+    c->wrap_any = true;
+  }
+  c->chunksw.clear();
+  c->cw_begin.assign(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) {
+    c->cw_begin[b] = (int)c->chunksw.size();
+    for (size_t x = 0; x < c->xfers.size(); ++x) {
+      const TransferDev& t = c->xfers[x];
+      if (t.rblock != b) continue;
+      const bool through = t.dblock == b && t.orient == 0 && (c->blocks[b].wrap >> (t.rface >> 1) & 1) &&
+                           (t.rface >> 1) == (t.dface >> 1) && t.rface != t.dface;
+      if (!through) add_chunks(c->chunksw, 3, (int)x, NG * t.len0 * t.len1);
+    }
+    for (size_t p = 0; p < c->patches.size(); ++p)
+      if (c->patches[p].block == b) add_chunks(c->chunksw, 1, (int)p, NG * c->patches[p].len0 * c->patches[p].len1);
+  }
+  c->cw_begin[nb] = (int)c->chunksw.size();
 
   // --- tiles per variant -------------------------------------------------------
   int nvar_t = 0;
@@ -703,6 +738,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->off_chunks1 = take(c->chunks1.size() * sizeof(ChunkDev));
   c->off_chunks2 = take(c->chunks2.size() * sizeof(ChunkDev));
   c->off_chunksd = take(c->chunksd.size() * sizeof(ChunkDev));
+  c->off_chunksw = take(c->chunksw.size() * sizeof(ChunkDev));
   c->off_export = take(c->export_off.size() * sizeof(long long));
   c->off_tiles_batched.assign(nvar_t, 0);
   c->off_tiles_block.assign(nvar_t, 0);
@@ -875,6 +911,7 @@ extern "C" cfd_status cfd_bind_workspace(cfd_ctx* c, void* ptr, size_t bytes) {
   if ((s = upload(c, c->off_chunks1, c->chunks1)) != CFD_OK) return s;
   if ((s = upload(c, c->off_chunks2, c->chunks2)) != CFD_OK) return s;
   if ((s = upload(c, c->off_chunksd, c->chunksd)) != CFD_OK) return s;
+  if ((s = upload(c, c->off_chunksw, c->chunksw)) != CFD_OK) return s;
   if ((s = upload(c, c->off_export, c->export_off)) != CFD_OK) return s;
   for (int v = 0; v < c->nvariants; ++v) {
     if ((s = upload(c, c->off_tiles_batched[v], c->tiles_batched[v])) != CFD_OK) return s;
@@ -981,23 +1018,30 @@ static StageArgs stage_args(cfd_ctx* c) {
   a.phi = c->frozen ? c->dptr<double>(c->off_phi) : nullptr;
   a.rv = c->viscous ? c->dptr<double>(c->off_rv) : nullptr;
   a.visc_cv = visc_cv(c);
+  a.wrap = c->frozen ? 0 : 1;  // (the frozen factors of ghost cells are read at the ghosts)
   return a;
 }
 
-static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s);
+static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only = false);
 
 // Ghost fill of state buffer q and, for the Navier-Stokes equations, the
 // viscous residual of q that the next stage-kernel launch subtracts.
-static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s) {
-  cfd_status st = fill_ghosts(c, q, s);
+// stencil_only: q is read by the stage kernel alone (see fill_ghosts).
+static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only = false) {
+  cfd_status st = fill_ghosts(c, q, s, stencil_only);
   if (st != CFD_OK || !c->viscous) return st;
   ViscArgs v = visc_args(c, q);
   HIP_TRY(c, launch_viscous(c->dim, v, s));
   return CFD_OK;
 }
 
-// Fill every ghost layer of state buffer q: pack + physical patches, then unpack.
-static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s) {
+// Fill every ghost layer of state buffer q: pack + physical patches, then
+// unpack (packed mode), or direct copies + physical patches (direct mode).
+// stencil_only (direct mode): q is read by the stage kernel alone, which reads
+// the periodic neighbours of a self-connected axis through the wrap, so those
+// connections are left out (their ghosts keep older values, or NaN with
+// CFD_NAN_GHOSTS).
+static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only) {
   GhostArgs g = ghost_args(c, q);
   const int nb = (int)c->blocks.size();
   if (c->cfg.debug_flags & CFD_NAN_GHOSTS) {
@@ -1006,15 +1050,17 @@ static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s) {
     HIP_TRY(c, launch_nan_ghosts(c->dim, n, c->max_padded, nb, s));
   }
   if (c->ghost_mode == CFD_GHOSTS_DIRECT) {
-    g.chunks = c->dptr<ChunkDev>(c->off_chunksd);
+    const bool w = stencil_only && c->wrap_any;
+    g.chunks = c->dptr<ChunkDev>(w ? c->off_chunksw : c->off_chunksd);
+    const std::vector<int>& begin = w ? c->cw_begin : c->cd_begin;
     if (c->exec_mode == CFD_EXEC_PER_BLOCK) {
       for (int b = 0; b < nb; ++b) {
-        g.chunk_begin = c->cd_begin[b];
-        HIP_TRY(c, launch_ghost(c->dim, g, c->cd_begin[b + 1] - c->cd_begin[b], s));
+        g.chunk_begin = begin[b];
+        HIP_TRY(c, launch_ghost(c->dim, g, begin[b + 1] - begin[b], s));
       }
     } else {
       g.chunk_begin = 0;
-      HIP_TRY(c, launch_ghost(c->dim, g, (int)c->chunksd.size(), s));
+      HIP_TRY(c, launch_ghost(c->dim, g, begin[nb], s));
     }
     return CFD_OK;
   }
@@ -1094,7 +1140,8 @@ static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
     // (a single stage writes into B and is copied back: the kernel reads its
     // input's neighbours while writing, so it never updates in place)
     double* out = (k == M && M > 1) ? A : ((k % 2) ? Bf : Cf);
-    cfd_status st = stage_prep(c, in, s);
+    // (an inviscid, unfrozen step reads its stage inputs in the stage kernel only)
+    cfd_status st = stage_prep(c, in, s, !c->viscous && !c->frozen);
     if (st != CFD_OK) return st;
     StageArgs a = stage_args(c);
     a.qin = in;

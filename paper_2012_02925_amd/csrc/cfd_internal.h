@@ -21,6 +21,7 @@ struct BlockDev {
   int ni, nj, nk;
   int pi, pj;              // row pitch (doubles), rows per k-plane
   int wall_mask;           // bit f: face f carries a slip-wall patch; bit f + 8: a farfield patch
+  int wrap;                // bit d: axis d is connected to itself end to end (periodic, no reorientation)
   long long vstride;       // doubles between two padded arrays of this block
   long long origin;        // offset of interior (0,0,0) of array 0 within a state buffer
   long long morigin;       // offset of interior (0,0,0) of metric array 0 within the metric buffer

@@ -66,6 +66,7 @@ struct StageArgs {
   const double* phi;     // frozen limiter factors (LIM_FROZEN): padded arrays d * nvar + v
   const double* rv;      // viscous residual (momentum.., energy), packed, subtracted from R; or null
   double visc_cv;        // viscous time-step coefficient 4 max(4/3, gamma/Pr) mu (0: inviscid)
+  int wrap;              // read periodic neighbours through the wrap of the block (BlockDev::wrap)
 };
 
 __device__ __forceinline__ double wall_pressure(double p0, double p1) { return 1.5 * p0 - 0.5 * p1; }
@@ -221,8 +222,16 @@ stage_kernel(StageArgs a) {
     // issued without a branch (conditionally issued loads make the compiler
     // wait for all outstanding loads, prefetches included, where the paths
     // join)
-    const long long oc = (own_in_pad ? pidx(B, i, j, 0) : 0) + K;
+    // Along an axis that the block connects to itself end to end, the stencil
+    // reads the cells that the ghost cells copy (the same values), so the
+    // ghost fill between stages can leave those connections out.
+    const int wrap = a.wrap ? B.wrap : 0;
+    auto wrapc = [](int x, int n, bool on) { return on ? (x < 0 ? x + n : (x >= n ? x - n : x)) : x; };
+    const long long oc =
+        (own_in_pad ? pidx(B, wrapc(i, B.ni, wrap & 1), wrapc(j, B.nj, wrap & 2), 0) : 0) + K;
     auto zoff = [&](int k) { return (unsigned)((oc + (long long)k * plane) * 8); };
+    // the k-queue's planes (ghost planes k < 0, k >= nk through the wrap)
+    auto zq = [&](int k) { return zoff(wrapc(k, B.nk, DIM == 3 && (wrap & 4))); };
 
     // this thread's halo-ring items (the same for every plane of the tile)
     int hpos[NH];
@@ -247,7 +256,7 @@ stage_kernel(StageArgs a) {
         const int ii = i0 - 2 + lx, jj = j0 - 2 + ly;
         if (ii <= B.ni + 1 && jj <= B.nj + 1) {
           hpos[h] = ly * LX + lx;
-          hoff[h] = (unsigned)((pidx(B, ii, jj, 0) + K) * 8);
+          hoff[h] = (unsigned)((pidx(B, wrapc(ii, B.ni, wrap & 1), wrapc(jj, B.nj, wrap & 2), 0) + K) * 8);
         }
       }
     }
@@ -335,14 +344,14 @@ stage_kernel(StageArgs a) {
         double q2[NV], Sz[3];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          qc[v] = ld_at(qin + v * vs, zoff(kbeg - 2));
-          qn[v] = ld_at(qin + v * vs, zoff(kbeg - 1));
+          qc[v] = ld_at(qin + v * vs, zq(kbeg - 2));
+          qn[v] = ld_at(qin + v * vs, zq(kbeg - 1));
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q2[v] = ld_at(qin + v * vs, zoff(kbeg));
+        for (int v = 0; v < NV; ++v) q2[v] = ld_at(qin + v * vs, zq(kbeg));
         zstep(kbeg - 2, qc, q2, nullptr, nullptr);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q2[v] = ld_at(qin + v * vs, zoff(kbeg + 1));
+        for (int v = 0; v < NV; ++v) q2[v] = ld_at(qin + v * vs, zq(kbeg + 1));
 #pragma unroll
         for (int c = 0; c < 3; ++c) Sz[c] = ld_at(met + ML::S(2, c) * vs, zoff(kbeg));
         if constexpr (DT) {
@@ -354,7 +363,7 @@ stage_kernel(StageArgs a) {
         for (int v = 0; v < NV; ++v) fzs[v][tid] = fzd[v];
         // queue now: qc = q(kbeg), qn = q(kbeg+1), scp = slope(kbeg)
 #pragma unroll
-        for (int v = 0; v < NV; ++v) qnx[v] = ld_at(qin + v * vs, zoff(kbeg + 2));
+        for (int v = 0; v < NV; ++v) qnx[v] = ld_at(qin + v * vs, zq(kbeg + 2));
       }
     }
     fetch_halo(kbeg);
@@ -603,7 +612,7 @@ stage_kernel(StageArgs a) {
           fzd[v] = fz[v] - fzs[v][tid];
           fzs[v][tid] = fz[v];
         }
-        const unsigned o3 = ok + (k + 1 < kend ? 3u * p8 : 0u);
+        const unsigned o3 = k + 1 < kend ? zq(k + 3) : ok;
 #pragma unroll
         for (int v = 0; v < NV; ++v) qnx[v] = ld_at(qin + v * vs, o3);
       }
