@@ -587,6 +587,15 @@ stage_kernel(StageArgs a) {
       double w0[NV], adtc = adt;
       const long long pcell = B.packed + (own ? ((long long)k * B.nj + j) * B.ni + i : 0);
       const double iv = ld_nt(met + ML::INVVOL * vs, ok);
+      // (DT) the cell's high i- and j-face area vectors, consumed after the next barrier
+      double shi[DT ? 2 : 1][DIM];
+      if constexpr (DT) {
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc) {
+          shi[0][cc] = ld_at(met + ML::S(0, cc) * vs, ok + 8u);
+          shi[1][cc] = ld_at(met + ML::S(1, cc) * vs, ok + 8u * B.pi);
+        }
+      }
       if (update && a.dtloc) adtc = a.alpha * a.dtloc[pcell];
       if (update && !q0_is_qin) {
         const double* q0 = a.q0 + (B.origin - K);
@@ -621,13 +630,14 @@ stage_kernel(StageArgs a) {
       // ---- 4. divergence and update ---------------------------------------
       // (DT) mean area vectors Sbar_d of the cell, ahead of the divergence:
       // the own low i- and j-faces (Sx, Sy) and both k-faces (szlo, Sz) are
-      // still in registers, only the high i- and j-faces are loaded
+      // still in registers, the high i- and j-faces were loaded before the
+      // barrier above
       double sbar[DT ? DIM : 1][DIM];
       if constexpr (DT) {
 #pragma unroll
         for (int cc = 0; cc < DIM; ++cc) {
-          sbar[0][cc] = 0.5 * (Sx[cc] + ld_at(met + ML::S(0, cc) * vs, ok + 8u));
-          sbar[1][cc] = 0.5 * (Sy[cc] + ld_at(met + ML::S(1, cc) * vs, ok + 8u * B.pi));
+          sbar[0][cc] = 0.5 * (Sx[cc] + shi[0][cc]);
+          sbar[1][cc] = 0.5 * (Sy[cc] + shi[1][cc]);
           if constexpr (DIM == 3) {
             sbar[2][cc] = 0.5 * (szlo[cc] + Sz[cc]);
             szlo[cc] = Sz[cc];
