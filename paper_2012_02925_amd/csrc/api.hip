@@ -1392,13 +1392,17 @@ extern "C" cfd_status cfd_autotune(cfd_ctx* c, int reps, int* chosen) {
   if (reps < 1) reps = 1;
   s = stage_prep(c, c->stA(), c->stream);
   if (s != CFD_OK) return s;
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(c, hipEventCreate(&e0));
-  HIP_TRY(c, hipEventCreate(&e1));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, CFD_ERR_HIP, "hipEventCreate failed");
+  }
   const int keep = c->variant;
   int best = keep;
   float best_ms = 1e30f;
-  for (int v = 0; v < c->nvariants; ++v) {
+  hipError_t he = hipSuccess;
+  for (int v = 0; v < c->nvariants && s == CFD_OK && he == hipSuccess; ++v) {
     c->variant = v;
     StageArgs a = stage_args(c);
     a.qin = c->stA();
@@ -1408,12 +1412,13 @@ extern "C" cfd_status cfd_autotune(cfd_ctx* c, int reps, int* chosen) {
     a.alpha = 0.25;
     a.dtmin = nullptr;
     if ((s = launch_stage_all(c, a, c->stream, false)) != CFD_OK) break;  // warm-up
-    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    if ((he = hipEventRecord(e0, c->stream)) != hipSuccess) break;
     for (int r = 0; r < reps && s == CFD_OK; ++r) s = launch_stage_all(c, a, c->stream, false);
-    HIP_TRY(c, hipEventRecord(e1, c->stream));
-    HIP_TRY(c, hipEventSynchronize(e1));
+    if (s != CFD_OK) break;
     float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+    if ((he = hipEventRecord(e1, c->stream)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess ||
+        (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+      break;
     if (ms < best_ms) {
       best_ms = ms;
       best = v;
@@ -1421,7 +1426,8 @@ extern "C" cfd_status cfd_autotune(cfd_ctx* c, int reps, int* chosen) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->variant = best;
+  if (s == CFD_OK && he != hipSuccess) s = fail(c, CFD_ERR_HIP, "autotune timing: %s", hipGetErrorString(he));
+  c->variant = s == CFD_OK ? best : keep;
   release_graph(c);
   if (chosen) *chosen = best;
   return s;

@@ -639,3 +639,21 @@ def test_periodic_wrap_with_filled_connections_all_modes():
     ok, rep = compare_state(outs[0][1], Qref, q_ref(case))
     _say("  ", rep)
     assert ok, rep
+
+
+def test_autotune_picks_a_variant_and_keeps_the_bits():
+    """cfd_autotune times every tile variant on the current state and keeps
+    the fastest: the chosen index is valid and selected, and the run after it
+    is bit for bit the run with any fixed variant."""
+    case = synth.jittered_periodic_box(dims=(40, 36, 34), seed=4)
+    s = _solver(case)
+    v = s.autotune(3)
+    assert 0 <= v < s.query("nvariants") and s.query("variant") == v
+    s.rk_step(3)
+    Q1 = s.get_state().cpu()
+    s.close()
+    s = _solver(case)
+    s.set_variant(0)
+    s.rk_step(3)
+    assert torch.equal(Q1, s.get_state().cpu())
+    s.close()
