@@ -19,6 +19,10 @@
   two area vectors in direction d, evaluated once per step from Q^n.
 * Runge-Kutta: Sec. 2, the explicit M-step scheme of Jameson, Schmidt and
   Turkel: Q^(k) = Q^(0) - alpha_k dt R(Q^(k-1)), alpha_k = 1/(M - k + 1).
+  Optionally (rk_scheme "classic4", not in the paper) the classical
+  fourth-order Runge-Kutta method written from its textbook definition:
+  k_i = -R(Y_i) with Y_1 = Q^n, Y_2 = Q^n + dt/2 k_1, Y_3 = Q^n + dt/2 k_2,
+  Y_4 = Q^n + dt k_3, and Q^(n+1) = Q^n + dt/6 (k_1 + 2 k_2 + 2 k_3 + k_4).
 * Objective: J = sum over slip-wall faces of p_w |S| (integrated wall pressure).
 * Laminar Navier-Stokes (viscosity > 0): R = R_inviscid - Rv with the
   viscous residual of oracle/viscous.py; no-slip walls take the inviscid wall
@@ -60,6 +64,7 @@ class Problem:
         self.efix = sch.efix
         self.flux = getattr(sch, "flux", "roe")
         self.stages = sch.rk_stages
+        self.rk_scheme = getattr(sch, "rk_scheme", "mstage")
         self.cfl = sch.cfl
         self.dt_fixed = sch.dt_fixed
         self.local_dt = getattr(sch, "local_dt", False)
@@ -258,6 +263,8 @@ class Problem:
             dt = self.time_step(Q_list, met) if dt is None else dt
             dts = [dt] * len(Q_list)
         res = (lambda Qs: self.residual(Qs, met)) if residual_fn is None else residual_fn
+        if self.rk_scheme == "classic4":
+            return self._classic4(Q_list, dts, res), dt
         M = self.stages
         Q0 = Q_list
         Qk = Q_list
@@ -266,6 +273,14 @@ class Problem:
             R = res(Qk)
             Qk = [Q0[b] - alpha * dts[b] * R[b] for b in range(len(Q0))]
         return Qk, dt
+
+    def _classic4(self, Q0, dts, res):
+        nb = range(len(Q0))
+        k1 = [-r for r in res(Q0)]
+        k2 = [-r for r in res([Q0[b] + 0.5 * dts[b] * k1[b] for b in nb])]
+        k3 = [-r for r in res([Q0[b] + 0.5 * dts[b] * k2[b] for b in nb])]
+        k4 = [-r for r in res([Q0[b] + dts[b] * k3[b] for b in nb])]
+        return [Q0[b] + dts[b] / 6.0 * (k1[b] + 2.0 * k2[b] + 2.0 * k3[b] + k4[b]) for b in nb]
 
     def residual_norms(self, Q_list, met=None):
         """Root-mean-square residual per conservative variable over all cells

@@ -96,6 +96,7 @@ class Scheme:
     efix: float = 0.1  # Harten smoothing width as a fraction of the Roe-averaged sound speed
     flux: str = "roe"  # "roe" | "vanleer_fvs" | "steger_warming"
     rk_stages: int = 4
+    rk_scheme: str = "mstage"  # "mstage" (Sec. 2) or "classic4" (classical fourth-order Runge-Kutta)
     cfl: float = 0.5
     dt_fixed: Optional[float] = None  # None = global CFL time step recomputed every step
     local_dt: bool = False  # local time stepping: every cell with its own CFL step (steady runs)

@@ -187,6 +187,40 @@ def test_rk_amplification_polynomial(stages):
     assert torch.allclose(Q1[0], poly * Q0[0], rtol=1e-14)
 
 
+def test_classic4_amplification_polynomial():
+    """Classical RK4 on the linear residual R = lam Q: one step multiplies Q by
+    the degree-4 Taylor polynomial of exp(-lam dt)."""
+    c = synth.gaussian_bump_periodic(8, 8)
+    c.scheme.rk_scheme = "classic4"
+    P = Problem(c)
+    lam, dt = 0.7, 0.9
+    Q0 = P.initial_state()
+    Q1, _ = P.rk_step(Q0, dt=torch.tensor(dt), residual_fn=lambda Qs: [lam * Q for Q in Qs])
+    z = -lam * dt
+    poly = sum(z ** m / math.factorial(m) for m in range(5))
+    assert torch.allclose(Q1[0], poly * Q0[0], rtol=1e-14)
+
+
+@pytest.mark.parametrize("scheme,order", [("classic4", 4), ("mstage", 2)])
+def test_rk_order_on_a_nonlinear_ode(scheme, order):
+    """dQ/dt = -Q^2 from Q = 1 to t = 1 (exact 1/2) with the residual
+    R(Q) = Q^2: halving dt divides the error by 2^order -- four for the
+    classical method, two for the four-stage scheme of Sec. 2 (fourth order
+    only for linear problems).  A wrong weight or node in either scheme
+    changes the ratio."""
+    c = synth.gaussian_bump_periodic(4, 4)
+    c.scheme.rk_scheme = scheme
+    P = Problem(c)
+    errs = []
+    for n in (20, 40, 80):
+        Q = [torch.ones_like(q) for q in P.initial_state()]
+        for _ in range(n):
+            Q, _ = P.rk_step(Q, dt=torch.tensor(1.0 / n), residual_fn=lambda Qs: [q * q for q in Qs])
+        errs.append(float((Q[0] - 0.5).abs().max()))
+    for a, b in zip(errs, errs[1:]):
+        assert abs(math.log2(a / b) - order) < 0.1, (scheme, errs)
+
+
 @pytest.mark.parametrize("lim", ["vanleer", "vanalbada"])
 def test_entropy_wave_keeps_p_and_u_uniform(lim):
     c = synth.gaussian_bump_periodic(24, 24, limiter=lim)
