@@ -93,7 +93,7 @@ typedef struct {
                            for the symmetric limiters, the value is validated only */
   double lim_eps[5];    /* van Albada regularisation per primitive variable (rho,u,v[,w],p) */
   double efix;          /* Harten smoothing half-width as a fraction of the Roe sound speed; 0 = off */
-  int rk_stages;        /* M of the M-stage scheme, alpha_k = 1/(M-k+1); 1..8 */
+  int rk_stages;        /* M of the M-stage scheme, alpha_k = 1/(M-k+1); 1..8 (4 with CFD_RK_CLASSIC4) */
   int dt_mode;          /* CFD_DT_CFL | CFD_DT_FIXED | CFD_DT_LOCAL */
   double cfl;           /* CFL number for CFD_DT_CFL and CFD_DT_LOCAL */
   double dt_fixed;      /* time step for CFD_DT_FIXED */
@@ -104,7 +104,18 @@ typedef struct {
                            (rho_inf = c_inf = 1), mu = M_inf / Re per unit length; 0 = Euler */
   double prandtl;       /* Prandtl number (0.72) when viscosity > 0 */
   int debug_flags;      /* CFD_CHECK_FINITE | CFD_NAN_GHOSTS (0 for production runs) */
+  int rk_scheme;        /* CFD_RK_MSTAGE (Sec. 2) | CFD_RK_CLASSIC4 */
 } cfd_config;
+
+/* Runge-Kutta scheme (cfd_config.rk_scheme).  CFD_RK_MSTAGE: the M-stage
+ * scheme of Sec. 2, Q^(k) = Q^(0) - dt R(Q^(k-1)) / (M-k+1).  CFD_RK_CLASSIC4
+ * (not in the paper): the classical fourth-order method, stage inputs
+ * Y2 = Q - dt/2 R(Q), Y3 = Q - dt/2 R(Y2), Y4 = Q - dt R(Y3) and
+ * Q^(n+1) = Q - dt/6 (R(Q) + 2 R(Y2) + 2 R(Y3) + R(Y4)); needs rk_stages = 4,
+ * two more state buffers in the workspace, and has no step adjoint
+ * (cfd_rk_step_vjp and cfd_rk_step_record return CFD_ERR_UNSUPPORTED).  Any
+ * other value is CFD_ERR_ARG at cfd_create. */
+enum { CFD_RK_MSTAGE = 0, CFD_RK_CLASSIC4 = 1 };
 
 /* Debug checks (cfd_config.debug_flags; any other bit is CFD_ERR_ARG at
  * cfd_create).  With any flag set, cfd_rk_step does not use its captured graph.

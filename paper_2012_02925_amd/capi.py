@@ -14,6 +14,7 @@ STATUS = {0: "CFD_OK", -1: "CFD_ERR_ARG", -2: "CFD_ERR_STATE", -3: "CFD_ERR_TOPO
           -5: "CFD_ERR_HIP", -6: "CFD_ERR_NONFINITE", -7: "CFD_ERR_UNSUPPORTED"}
 LIM = {"none": 0, "vanleer": 1, "vanalbada": 2}
 FLUX = {"roe": 0, "vanleer_fvs": 1, "steger_warming": 2}
+RK = {"mstage": 0, "classic4": 1}
 BC = {"slip_wall": 1, "sup_inflow": 2, "extrap_outflow": 3, "farfield": 4, "sub_inflow": 5, "sub_outflow": 6,
       "noslip_wall": 7}
 DT_CFL, DT_FIXED, DT_LOCAL = 0, 1, 2
@@ -30,7 +31,7 @@ class CfdConfig(ctypes.Structure):
                 ("lim_eps", ctypes.c_double * 5), ("efix", ctypes.c_double), ("rk_stages", ctypes.c_int),
                 ("dt_mode", ctypes.c_int), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
                 ("flux", ctypes.c_int), ("viscosity", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("debug_flags", ctypes.c_int)]
+                ("debug_flags", ctypes.c_int), ("rk_scheme", ctypes.c_int)]
 
 
 class CfdError(RuntimeError):

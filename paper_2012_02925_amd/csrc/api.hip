@@ -86,6 +86,7 @@ struct cfd_ctx {
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  size_t off_rkD = 0, off_rkE = 0;  // classical RK4: stage input Y4 and Z = Q - dt/6 R(Y4)
   size_t off_stA = 0, off_stB = 0, off_stC = 0, off_metric = 0, off_nodes = 0, off_xbuf = 0, off_inflow = 0,
          off_dt = 0, off_dtmin = 0, off_err = 0, off_blocks = 0, off_xfers = 0, off_patches = 0, off_chunks1 = 0,
          off_chunks2 = 0, off_chunksd = 0, off_export = 0, off_chunksw = 0;
@@ -267,6 +268,8 @@ extern "C" cfd_status cfd_create(const cfd_config* cfg, void* stream, cfd_ctx** 
   if (cfg->limiter < CFD_LIM_NONE || cfg->limiter > CFD_LIM_VANALBADA) return CFD_ERR_ARG;
   if (cfg->flux < CFD_FLUX_ROE || cfg->flux > CFD_FLUX_STEGER_WARMING) return CFD_ERR_ARG;
   if (cfg->rk_stages < 1 || cfg->rk_stages > 8) return CFD_ERR_ARG;
+  if (cfg->rk_scheme != CFD_RK_MSTAGE && cfg->rk_scheme != CFD_RK_CLASSIC4) return CFD_ERR_ARG;
+  if (cfg->rk_scheme == CFD_RK_CLASSIC4 && cfg->rk_stages != 4) return CFD_ERR_ARG;
   if ((cfg->dt_mode == CFD_DT_CFL || cfg->dt_mode == CFD_DT_LOCAL) && !(cfg->cfl > 0.0)) return CFD_ERR_ARG;
   if (cfg->dt_mode == CFD_DT_FIXED && !(cfg->dt_fixed > 0.0)) return CFD_ERR_ARG;
   if (cfg->dt_mode != CFD_DT_CFL && cfg->dt_mode != CFD_DT_FIXED && cfg->dt_mode != CFD_DT_LOCAL)
@@ -705,6 +708,10 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->off_stA = take(c->state_doubles * 8);
   c->off_stB = take(c->state_doubles * 8);
   c->off_stC = take(c->state_doubles * 8);
+  if (c->cfg.rk_scheme == CFD_RK_CLASSIC4) {  // (inside the range zeroed at bind)
+    c->off_rkD = take(c->state_doubles * 8);
+    c->off_rkE = take(c->state_doubles * 8);
+  }
   c->off_metric = take(c->metric_doubles * 8);
   c->off_nodes = take((size_t)c->nnodes * dim * 8);
   c->off_xbuf = take(c->xbuf_doubles * 8);
@@ -1125,12 +1132,65 @@ static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool 
   return CFD_OK;
 }
 
+// Classical fourth-order Runge-Kutta step (CFD_RK_CLASSIC4): the stage kernel
+// writes Y2 = Q - dt/2 R(Q) into B, Y3 = Q - dt/2 R(Y2) into C,
+// Y4 = Q - dt R(Y3) into D and Z = Q - dt/6 R(Y4) into E; the combination
+// kernel forms Q^(n+1) in A, and the next step's Omega/lambda comes from it
+// (the cell time-step kernel, in place of the stage kernel's epilogue).
+static cfd_status enqueue_classic4(cfd_ctx* c, hipStream_t s, bool timed) {
+  double* A = c->stA();
+  double* buf[5] = {A, c->stB(), c->stC(), c->dptr<double>(c->off_rkD), c->dptr<double>(c->off_rkE)};
+  const double alpha[4] = {0.5, 0.5, 1.0, 1.0 / 6.0};
+  for (int k = 0; k < 4; ++k) {
+    cfd_status st = stage_prep(c, buf[k], s, !c->viscous && !c->frozen);
+    if (st != CFD_OK) return st;
+    StageArgs a = stage_args(c);
+    a.qin = buf[k];
+    a.q0 = A;
+    a.qout = buf[k + 1];
+    a.mode = MODE_STAGE;
+    a.alpha = alpha[k];
+    a.dtmin = nullptr;
+    if ((st = launch_stage_all(c, a, s, timed)) != CFD_OK) return st;
+  }
+  Rk4Args r{};
+  r.blocks = c->dptr<BlockDev>(c->off_blocks);
+  r.q = A;
+  r.y2 = buf[1];
+  r.y3 = buf[2];
+  r.y4 = buf[3];
+  r.z = buf[4];
+  r.out = A;
+  r.gas = make_gas(c->cfg.gamma);
+  const int nb = (int)c->blocks.size();
+  HIP_TRY(c, launch_rk4_combine(c->dim, r, c->max_cells, nb, s));
+  CellArgs ca = cell_args(c);
+  if (c->cfg.debug_flags & CFD_CHECK_FINITE) {
+    for (int k = 1; k < 5; ++k) {
+      ca.src = buf[k];
+      HIP_TRY(c, launch_check_state(c->dim, ca, c->max_cells, nb, s));
+    }
+    ca.src = A;
+    HIP_TRY(c, launch_check_state(c->dim, ca, c->max_cells, nb, s));
+  }
+  if (c->cfg.dt_mode != CFD_DT_FIXED) {  // (the step's dt_promote left dtmin at +inf)
+    ca.src = A;
+    if (c->cfg.dt_mode == CFD_DT_LOCAL) {
+      ca.dtloc = c->dptr<double>(c->off_dtloc);
+      ca.cfl = c->cfg.cfl;
+    }
+    HIP_TRY(c, launch_cell_dt(c->dim, ca, c->max_cells, nb, s));
+  }
+  return CFD_OK;
+}
+
 // Enqueue one full Runge-Kutta step on stream s.
 static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
   const bool cfl = c->cfg.dt_mode != CFD_DT_FIXED;
   if (cfl)
     HIP_TRY(c, launch_dt_promote(c->dptr<double>(c->off_dt), c->dptr<unsigned long long>(c->off_dtmin), c->cfg.cfl, 1,
                                  nullptr, s));
+  if (c->cfg.rk_scheme == CFD_RK_CLASSIC4) return enqueue_classic4(c, s, timed);
   const int M = c->cfg.rk_stages;
   double* A = c->stA();
   double* Bf = c->stB();
@@ -1637,6 +1697,8 @@ extern "C" cfd_status cfd_residual_vjp(cfd_ctx* c, const double* dev_Rbar, doubl
 static cfd_status step_vjp_checks(cfd_ctx* c) {
   cfd_status s = need_adjoint(c);
   if (s != CFD_OK) return s;
+  if (c->cfg.rk_scheme != CFD_RK_MSTAGE)
+    return fail(c, CFD_ERR_UNSUPPORTED, "the step adjoint covers the M-stage scheme (CFD_RK_MSTAGE)");
   if (c->cfg.dt_mode != CFD_DT_FIXED)
     return fail(c, CFD_ERR_UNSUPPORTED, "the step adjoint needs a fixed time step (CFD_DT_FIXED)");
   if (c->cfg.rk_stages > 4) return fail(c, CFD_ERR_UNSUPPORTED, "the step adjoint keeps at most 4 stage states");
@@ -1674,6 +1736,8 @@ extern "C" cfd_status cfd_rk_step_record(cfd_ctx* c, void* dev_stages) {
   cfd_status s = need(c, true, true);
   if (s != CFD_OK) return s;
   if (!dev_stages) return CFD_ERR_ARG;
+  if (c->cfg.rk_scheme != CFD_RK_MSTAGE)
+    return fail(c, CFD_ERR_UNSUPPORTED, "stage recording covers the M-stage scheme (CFD_RK_MSTAGE)");
   if (!c->have_state) return fail(c, CFD_ERR_STATE, "no state set");
   if ((s = ensure_dt(c)) != CFD_OK) return s;
   const bool cfl = c->cfg.dt_mode != CFD_DT_FIXED;

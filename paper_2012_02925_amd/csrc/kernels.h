@@ -38,6 +38,18 @@ struct CellArgs {
   double visc_cv;  // viscous time-step coefficient (0: inviscid)
 };
 
+// Classical fourth-order Runge-Kutta combination (primitive padded states).
+struct Rk4Args {
+  const BlockDev* blocks;
+  const double* q;   // step input Q
+  const double* y2;  // Q - dt/2 R(Q)
+  const double* y3;  // Q - dt/2 R(Y2)
+  const double* y4;  // Q - dt R(Y3)
+  const double* z;   // Q - dt/6 R(Y4)
+  double* out;       // Q^(n+1) (may be q)
+  Gas gas;
+};
+
 struct MetricArgs {
   const BlockDev* blocks;
   const double* nodes;
@@ -82,6 +94,7 @@ hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream
 // non-finite entry of a packed array
 hipError_t launch_nan_ghosts(int dim, const CellArgs& a, long long max_padded, int nblocks, hipStream_t s);
 hipError_t launch_check_state(int dim, const CellArgs& a, long long max_cells, int nblocks, hipStream_t s);
+hipError_t launch_rk4_combine(int dim, const Rk4Args& a, long long max_cells, int nblocks, hipStream_t s);
 hipError_t launch_check_packed(const double* x, long long n, int* err, hipStream_t s);
 hipError_t launch_copy_dt(const double* src, double* dst, hipStream_t s);
 

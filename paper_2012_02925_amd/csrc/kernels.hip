@@ -662,6 +662,56 @@ __global__ void __launch_bounds__(256) check_state_kernel(CellArgs a) {
   if (!ok) atomicOr(a.err, 1);
 }
 
+// Classical fourth-order Runge-Kutta (not in the paper; the M-stage scheme of
+// Sec. 2 is the default): with the stage inputs Y2, Y3, Y4 and
+// Z = Q - dt/6 R(Y4) written by the stage kernel, per interior cell in
+// conservative variables
+//   Q^(n+1) = Q + [(Y2 - Q) + 2 (Y3 - Q) + (Y4 - Q)] / 3 + (Z - Q)
+//           = Q - dt/6 (R(Q) + 2 R(Y2) + 2 R(Y3) + R(Y4)).
+// Each difference is a multiple of dt R, so a steady state stays exactly
+// steady.  out may alias q (each cell reads its own values first).
+template <int DIM>
+__global__ void __launch_bounds__(256) rk4_combine_kernel(Rk4Args a) {
+  constexpr int NV = DIM + 2;
+  const BlockDev B = a.blocks[blockIdx.y];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (!cell_of(B, c, i, j, k)) return;
+  const long long p = B.origin + pidx(B, i, j, k), vs = B.vstride;
+  double w[NV], Q[NV], Y[NV], acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) w[v] = a.q[v * vs + p];
+  prim_to_cons<DIM>(w, a.gas, Q);
+  const double* src[3] = {a.y2, a.y3, a.y4};
+  const double wt[3] = {1.0, 2.0, 1.0};
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = src[s][v * vs + p];
+    prim_to_cons<DIM>(w, a.gas, Y);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += wt[s] * (Y[v] - Q[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) w[v] = a.z[v * vs + p];
+  prim_to_cons<DIM>(w, a.gas, Y);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Y[v] = Q[v] + acc[v] / 3.0 + (Y[v] - Q[v]);
+  cons_to_prim<DIM>(Y, a.gas, w);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) a.out[v * vs + p] = w[v];
+}
+
+hipError_t launch_rk4_combine(int dim, const Rk4Args& a, long long max_cells, int nblocks, hipStream_t s) {
+  if (dim == 2)
+    hipLaunchKernelGGL(rk4_combine_kernel<2>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(rk4_combine_kernel<3>, cell_grid(max_cells, nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 // CFD_CHECK_FINITE: flag a non-finite entry of a packed array (n doubles).
 __global__ void __launch_bounds__(256) check_packed_kernel(const double* x, long long n, int* err) {
   bool ok = true;

@@ -27,6 +27,7 @@ def config_from_scheme(dim, scheme, debug_flags=0):
         cfg.lim_eps[v] = float(le[v]) if v < len(le) else 0.0
     cfg.efix = scheme.efix
     cfg.rk_stages = scheme.rk_stages
+    cfg.rk_scheme = capi.RK[getattr(scheme, "rk_scheme", "mstage")]
     cfg.flux = capi.FLUX[getattr(scheme, "flux", "roe")]
     cfg.viscosity = float(getattr(scheme, "viscosity", 0.0))
     cfg.prandtl = float(getattr(scheme, "prandtl", 0.72))

@@ -82,6 +82,12 @@ def test_config_validation():
     assert lib.cfd_create(ctypes.byref(_cfg(capi, rk_stages=0)), None, ctypes.byref(ctx)) == -1
     assert lib.cfd_create(ctypes.byref(_cfg(capi, cfl=0.0)), None, ctypes.byref(ctx)) == -1
     assert lib.cfd_create(ctypes.byref(_cfg(capi, limiter=7)), None, ctypes.byref(ctx)) == -1
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, rk_scheme=2)), None, ctypes.byref(ctx)) == -1
+    # the classical fourth-order method has exactly four stages
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, rk_scheme=capi.RK["classic4"], rk_stages=3)), None,
+                          ctypes.byref(ctx)) == -1
+    assert lib.cfd_create(ctypes.byref(_cfg(capi, rk_scheme=capi.RK["classic4"])), None, ctypes.byref(ctx)) == 0
+    lib.cfd_destroy(ctx)
 
 
 def test_flux_selection_validation():

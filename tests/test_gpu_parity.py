@@ -657,3 +657,63 @@ def test_autotune_picks_a_variant_and_keeps_the_bits():
     s.rk_step(3)
     assert torch.equal(Q1, s.get_state().cpu())
     s.close()
+
+
+def _classic4(case):
+    case.scheme.rk_scheme = "classic4"
+    case.scheme.rk_stages = 4
+    return case
+
+
+CLASSIC4_CASES = {
+    "box3d_20x18x16": lambda: synth.jittered_periodic_box(dims=(20, 18, 16), seed=3),
+    "ramp_64x40": lambda: synth.compression_ramp(64, 40),
+    "patchwork_3x2": lambda: synth.patchwork(seed=3, nbx=3, nby=2, side_lo=10, side_hi=30, h=1.0 / 48),
+    "ramp_local_dt": lambda: synth.compression_ramp(48, 32, limiter="vanalbada"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CLASSIC4_CASES))
+def test_classic4_matches_oracle(name):
+    """CFD_RK_CLASSIC4 (classical fourth-order Runge-Kutta): 12 steps, state
+    and per-step time step against the oracle's textbook implementation."""
+    case = _classic4(CLASSIC4_CASES[name]())
+    if name == "ramp_local_dt":
+        case.scheme.local_dt = True
+    Qref, dref = oracle_run(case, 12)
+    s = _solver(case)
+    dt = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    dts = []
+    for _ in range(12):
+        s.rk_step(1, dt)
+        dts.append(dt.item())
+    ok, rep = compare_state(s.get_state(), Qref, q_ref(case))
+    _say("  classic4", name, rep)
+    assert ok, rep
+    assert max(abs(a - b) / b for a, b in zip(dts, dref)) <= 1e-12
+
+
+def test_classic4_modes_bitwise_and_no_step_adjoint():
+    """The classical scheme in every launch mode, both exchanges and with
+    NaN-filled ghosts gives the same bits; the step adjoint and stage
+    recording report CFD_ERR_UNSUPPORTED."""
+    from paper_2012_02925_amd import capi
+    case = _classic4(_rotated_two_block_box())
+    outs = []
+    for mode, graph, ghosts, flags in [("batched", True, "direct", 0), ("per_block", False, "direct", 0),
+                                       ("persistent", True, "direct", 0), ("batched", False, "packed", 0),
+                                       ("batched", False, "direct", capi.NAN_GHOSTS | capi.CHECK_FINITE)]:
+        s = _solver(case, debug_flags=flags)
+        s.set_exec(mode, graph)
+        s.set_ghost_exchange(ghosts)
+        s.rk_step(6)
+        outs.append(((mode, graph, ghosts, flags), s.get_state().cpu()))
+        s.close()
+    for key, o in outs[1:]:
+        assert torch.equal(outs[0][1], o), key
+    ramp = _classic4(synth.compression_ramp(24, 16, dt_fixed=1e-3))
+    s = _solver(ramp, adjoint=True)
+    with pytest.raises(capi.CfdError) as e:
+        s.rk_step_vjp(torch.zeros((ramp.nvar, ramp.ncells), dtype=torch.float64, device="cuda:0"))
+    assert e.value.status == -7
+    s.close()
