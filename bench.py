@@ -503,7 +503,11 @@ def main():
                      "kernel": "cfd::stage_kernel", "bytes_per_cell_stage": BYTES_PER_CELL_STAGE[dim],
                      "mean_launch_ms": mean_launch_s * 1e3, "launches": launches,
                      "practical_ceiling_gbs": None if ceiling is None else ceiling["gbs"],
-                     "frac_of_practical_ceiling": None if ceiling is None else achieved / ceiling["gbs"]},
+                     "frac_of_practical_ceiling": None if ceiling is None else achieved / ceiling["gbs"],
+                     # the counters' bytes (reads + writes) over the same launch time
+                     "traffic_gbs": None if traffic is None else traffic["bytes_per_launch"] / mean_launch_s / 1e9,
+                     "traffic_frac": None if traffic is None else
+                     traffic["bytes_per_launch"] / mean_launch_s / 1e9 / HBM_PEAK_GBS},
         "timing": {"repeats": args.repeats, "steps_per_repeat": args.steps,
                    "ms_per_step_each": [w * 1e3 / args.steps for w in walls],
                    "event_ms_per_step_each": [r["event_ms"] / args.steps for r in reps],
