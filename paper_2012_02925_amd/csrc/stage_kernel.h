@@ -222,16 +222,23 @@ stage_kernel(StageArgs a) {
     // issued without a branch (conditionally issued loads make the compiler
     // wait for all outstanding loads, prefetches included, where the paths
     // join)
+    const long long oc = (own_in_pad ? pidx(B, i, j, 0) : 0) + K;
+    // (metrics, stage-start state and output of the lane's cell, plane k)
+    auto zoff = [&](int k) { return (unsigned)((oc + (long long)k * plane) * 8); };
     // Along an axis that the block connects to itself end to end, the stencil
     // reads the cells that the ghost cells copy (the same values), so the
-    // ghost fill between stages can leave those connections out.
+    // ghost fill between stages can leave those connections out.  Only state
+    // values are read through the wrap: a lane on a ghost cell of the high
+    // side still takes the area vector of its own low face, the block's
+    // boundary face, from its unwrapped position.
     const int wrap = a.wrap ? B.wrap : 0;
     auto wrapc = [](int x, int n, bool on) { return on ? (x < 0 ? x + n : (x >= n ? x - n : x)) : x; };
-    const long long oc =
+    const long long ocq =
         (own_in_pad ? pidx(B, wrapc(i, B.ni, wrap & 1), wrapc(j, B.nj, wrap & 2), 0) : 0) + K;
-    auto zoff = [&](int k) { return (unsigned)((oc + (long long)k * plane) * 8); };
-    // the k-queue's planes (ghost planes k < 0, k >= nk through the wrap)
-    auto zq = [&](int k) { return zoff(wrapc(k, B.nk, DIM == 3 && (wrap & 4))); };
+    // the lane's state in plane k (the k-queue's ghost planes k < 0, k >= nk through the wrap)
+    auto zq = [&](int k) {
+      return (unsigned)((ocq + (long long)wrapc(k, B.nk, DIM == 3 && (wrap & 4)) * plane) * 8);
+    };
 
     // this thread's halo-ring items (the same for every plane of the tile)
     int hpos[NH];
@@ -393,8 +400,9 @@ stage_kernel(StageArgs a) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) sq[v][own_lp] = qc[v];
       } else if (own_in_pad) {
+        const unsigned okq = zq(k);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sq[v][own_lp] = ld_at(qin + v * vs, ok);
+        for (int v = 0; v < NV; ++v) sq[v][own_lp] = ld_at(qin + v * vs, okq);
       }
 #pragma unroll
       for (int h = 0; h < NH; ++h) {
@@ -621,7 +629,7 @@ stage_kernel(StageArgs a) {
           fzd[v] = fz[v] - fzs[v][tid];
           fzs[v][tid] = fz[v];
         }
-        const unsigned o3 = k + 1 < kend ? zq(k + 3) : ok;
+        const unsigned o3 = zq(k + 1 < kend ? k + 3 : k);
 #pragma unroll
         for (int v = 0; v < NV; ++v) qnx[v] = ld_at(qin + v * vs, o3);
       }
