@@ -1102,6 +1102,19 @@ static EventPair& next_event(cfd_ctx* c) {
   return c->ev_pool[c->ev_used++];
 }
 
+// Limiter instantiation of the stage kernel: frozen factors, van Albada with
+// every regularisation zero (the specialisation without e^2), or the
+// configured limiter.
+static int stage_limiter(const cfd_ctx* c) {
+  if (c->frozen) return LIM_FROZEN;
+  if (c->cfg.limiter == CFD_LIM_VANALBADA) {
+    bool zero = true;
+    for (int v = 0; v < c->nvar; ++v) zero = zero && c->cfg.lim_eps[v] == 0.0;
+    if (zero) return LIM_VANALBADA0;
+  }
+  return c->cfg.limiter;
+}
+
 static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool timed) {
   const int v = c->variant;
   const int nb = (int)c->blocks.size();
@@ -1115,14 +1128,14 @@ static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool 
     for (int b = 0; b < nb; ++b) {
       a.tile_begin = c->tile_begin[v][b];
       a.tile_end = c->tile_begin[v][b + 1];
-      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->frozen ? LIM_FROZEN : c->cfg.limiter, v, c->has_farfield, a,
+      HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, stage_limiter(c), v, c->has_farfield, a,
                               a.tile_end - a.tile_begin, false, s));
     }
   } else {
     a.tiles = c->dptr<TileDev>(c->off_tiles_batched[v]);
     a.tile_begin = 0;
     a.tile_end = (int)c->tiles_batched[v].size();
-    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, c->frozen ? LIM_FROZEN : c->cfg.limiter, v, c->has_farfield, a,
+    HIP_TRY(c, launch_stage(c->dim, c->cfg.flux, stage_limiter(c), v, c->has_farfield, a,
                             a.tile_end, c->exec_mode == CFD_EXEC_PERSISTENT, s));
   }
   if (timed) {

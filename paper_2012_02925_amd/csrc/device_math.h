@@ -54,7 +54,10 @@ __device__ __forceinline__ double rsq2(double x) {
 // every kappa of eq. (flux).  A denominator below 1e-250 returns 0: the
 // differences are then below 1e-250 (van Leer) or 1e-125 (van Albada without
 // regularisation) and so is the exact slope.
-enum { LIM_NONE = 0, LIM_VANLEER = 1, LIM_VANALBADA = 2, LIM_FROZEN = 3 };
+// LIM_VANALBADA0: van Albada with every regularisation e = 0, a stage-kernel
+// specialisation with the e^2 terms compiled out (the same bits: fma(a, a, 0)
+// is the rounded product), which frees the registers the e^2 values held.
+enum { LIM_NONE = 0, LIM_VANLEER = 1, LIM_VANALBADA = 2, LIM_FROZEN = 3, LIM_VANALBADA0 = 4 };
 constexpr double SLOPE_TINY = 1e-250;
 
 template <int LIM>
@@ -68,7 +71,8 @@ __device__ __forceinline__ double slope(double a, double b, double e2) {
     return den > SLOPE_TINY ? num * rcp(den) : 0.0;
   } else {
     // with A = a^2 + e^2, B = b^2 + e^2: S = (B a + A b) / (A + B)
-    const double A = fma(a, a, e2), B = fma(b, b, e2);
+    const double A = LIM == LIM_VANALBADA0 ? a * a : fma(a, a, e2);
+    const double B = LIM == LIM_VANALBADA0 ? b * b : fma(b, b, e2);
     const double den = A + B;
     const double num = fma(B, a, A * b);
     return den > SLOPE_TINY ? num * rcp(den) : 0.0;

@@ -44,6 +44,7 @@ inline hipError_t launch_stage_lim(int lim, bool ff, const StageArgs& a, int gri
     case LIM_NONE: return launch_stage_t<DIM, LIM_NONE, TX, TY, KC, FLUX>(ff, a, grid, pers, s);
     case LIM_VANLEER: return launch_stage_t<DIM, LIM_VANLEER, TX, TY, KC, FLUX>(ff, a, grid, pers, s);
     case LIM_FROZEN: return launch_stage_t<DIM, LIM_FROZEN, TX, TY, KC, FLUX>(ff, a, grid, pers, s);
+    case LIM_VANALBADA0: return launch_stage_t<DIM, LIM_VANALBADA0, TX, TY, KC, FLUX>(ff, a, grid, pers, s);
     default: return launch_stage_t<DIM, LIM_VANALBADA, TX, TY, KC, FLUX>(ff, a, grid, pers, s);
   }
 }
