@@ -719,7 +719,14 @@ CLASSIC4_CASES = {
     "ramp_64x40": lambda: synth.compression_ramp(64, 40),
     "patchwork_3x2": lambda: synth.patchwork(seed=3, nbx=3, nby=2, side_lo=10, side_hi=30, h=1.0 / 48),
     "ramp_local_dt": lambda: synth.compression_ramp(48, 32, limiter="vanalbada"),
+    "ns_box3d_20x18x16": lambda: _ns(synth.jittered_periodic_box(dims=(20, 18, 16), seed=5), 0.01),
 }
+
+
+def _ns(case, mu):
+    case.scheme.viscosity = mu
+    case.name += "_ns"
+    return case
 
 
 @pytest.mark.parametrize("name", sorted(CLASSIC4_CASES))
