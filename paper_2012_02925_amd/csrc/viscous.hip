@@ -451,8 +451,9 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
     // first NT of each kind, then the remaining NFX - NT x-faces and NFY - NT
     // y-faces in one shared round (on one wave instead of two rounds)
     static_assert(NFX - NT + NFY - NT <= 64, "leftover faces fit one wavefront");
-    // (a loop kept rolled: one face's arithmetic at a time in registers)
-#pragma unroll 1
+    // (unrolled, so the two faces' loads and arithmetic interleave: 231 VGPRs,
+    // still the two waves per SIMD that the LDS allows; 1.18 -> 1.13 ms on 256^3)
+#pragma unroll
     for (int r = 0; r < 2; ++r) xy_face(r == 0, tid);
     if (tid < NFX - NT + NFY - NT) {
       const bool isx = tid < NFX - NT;
