@@ -349,7 +349,9 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
 #pragma unroll
             for (int w = 0; w < 4; ++w) acc[w] += sc[sls][3 + w][c];
           }
-      const double rc = 1.0 / (double)cnt;
+      // 8 cells, or 6 on an edge of the block, 4 at a corner: the reciprocal
+      // from constants (the same bits as 1.0 / cnt, without a division)
+      const double rc = cnt == 8 ? 0.125 : (cnt == 6 ? 1.0 / 6.0 : 0.25);
 #pragma unroll
       for (int w = 0; w < 4; ++w) sn[slot][w][e] = acc[w] * rc;
     }
@@ -545,7 +547,8 @@ __global__ void __launch_bounds__(VT2* VT2) viscous_tile2d_kernel(ViscArgs a) {
 #pragma unroll
         for (int w = 0; w < 3; ++w) acc[w] += sc[2 + w][c];
       }
-    const double rc = 1.0 / (double)cnt;
+    // 4 cells, 3 at a corner of the block (the same bits as 1.0 / cnt)
+    const double rc = cnt == 4 ? 0.25 : 1.0 / 3.0;
 #pragma unroll
     for (int w = 0; w < 3; ++w) sn[w][e] = acc[w] * rc;
   }
