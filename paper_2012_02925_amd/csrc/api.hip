@@ -717,7 +717,7 @@ extern "C" cfd_status cfd_finalize(cfd_ctx* c, size_t* ws_bytes) {
   c->off_xbuf = take(c->xbuf_doubles * 8);
   c->off_inflow = take((size_t)std::max(c->nparam, 1) * MAXV * 8);
   c->off_dt = take(2 * 8);
-  c->off_dtmin = take(8);
+  c->off_dtmin = take(8 * DT_SLOTS);
   c->off_err = take(4);
   c->off_normpart = take((size_t)cfd_ctx::NORM_PARTS * MAXV * 8);
   if (c->cfg.dt_mode == CFD_DT_LOCAL) c->off_dtloc = take((size_t)c->ncells * 8);
@@ -1251,7 +1251,7 @@ static cfd_status debug_flagged(cfd_ctx* c, bool* bad) {
 
 static cfd_status ensure_dt(cfd_ctx* c) {
   if (c->cfg.dt_mode == CFD_DT_FIXED || c->dt_valid) return CFD_OK;
-  HIP_TRY(c, launch_set_u64(c->dptr<unsigned long long>(c->off_dtmin), 0x7ff0000000000000ULL, c->stream));
+  HIP_TRY(c, launch_set_u64(c->dptr<unsigned long long>(c->off_dtmin), 0x7ff0000000000000ULL, DT_SLOTS, c->stream));
   CellArgs a = cell_args(c);
   a.src = c->stA();
   if (c->cfg.dt_mode == CFD_DT_LOCAL) {

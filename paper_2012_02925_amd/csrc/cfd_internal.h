@@ -10,6 +10,11 @@ namespace cfd {
 constexpr int NG = 2;    // ghost layers: the four-cell MUSCL stencil of eq. (flux)
 constexpr int MAXV = 5;  // variables in 3D
 constexpr int FARFIELD_MASK_SHIFT = 1 << 8;  // BlockDev::wall_mask: farfield bits above the wall bits
+// The CFL time step's minimum of Omega/lambda is reduced into DT_SLOTS slots
+// (workgroup w into slot w mod DT_SLOTS, one atomic each) so that thousands
+// of workgroups do not all update one address; the promote kernel takes the
+// minimum over the slots (an exact minimum, whatever the order).
+constexpr int DT_SLOTS = 64;
 
 // One structured block in the workspace.  Every padded array of the block
 // (state variables, metric components) shares the same geometry:

@@ -88,7 +88,7 @@ hipError_t launch_export_padded(int dim, const CellArgs& a, long long max_padded
 hipError_t launch_metrics(int dim, const MetricArgs& a, long long max_pos, int nblocks, hipStream_t s);
 hipError_t launch_dt_promote(double* dt, unsigned long long* dtmin, double cfl, int promote, double* out,
                              hipStream_t s);
-hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
+hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t s);
 // debug checks: NaN into the ghost region of a state buffer (a.dst); flag
 // (a.err) a non-physical interior cell of a primitive buffer (a.src); flag a
 // non-finite entry of a packed array

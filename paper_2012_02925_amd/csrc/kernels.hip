@@ -323,22 +323,30 @@ __global__ void __launch_bounds__(256) cell_dt_kernel(CellArgs a) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double r = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
-    atomicMin(a.dtmin, (unsigned long long)__double_as_longlong(r));
+    const unsigned w = blockIdx.y * gridDim.x + blockIdx.x;
+    atomicMin(a.dtmin + w % DT_SLOTS, (unsigned long long)__double_as_longlong(r));
   }
 }
 
-// dt <- cfl * min (when promote) ; min <- +inf
-__global__ void dt_promote_kernel(double* dt, unsigned long long* dtmin, double cfl, int promote, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const double m = __longlong_as_double((long long)*dtmin);
+// dt <- cfl * min over the DT_SLOTS slots (when promote); slots <- +inf.
+// One wavefront: every lane reads one slot, the minimum is formed by
+// shuffles, and each lane resets its own slot after that.
+__global__ void __launch_bounds__(64) dt_promote_kernel(double* dt, unsigned long long* dtmin, double cfl, int promote,
+                                                        double* out) {
+  static_assert(DT_SLOTS == 64, "one slot per lane of the wavefront");
+  const int t = threadIdx.x;
+  double m = __longlong_as_double((long long)dtmin[t]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
+  if (t == 0) {
     if (promote) dt[0] = cfl * m;
     if (out) out[0] = cfl * m;
-    if (promote) *dtmin = (unsigned long long)__double_as_longlong(INFINITY);
   }
+  if (promote) dtmin[t] = (unsigned long long)__double_as_longlong(INFINITY);
 }
 
-__global__ void set_u64_kernel(unsigned long long* p, unsigned long long v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+__global__ void set_u64_kernel(unsigned long long* p, unsigned long long v, int n) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = v;
 }
 
 __global__ void copy_dt_kernel(const double* src, double* dst) {
@@ -773,8 +781,8 @@ hipError_t launch_dt_promote(double* dt, unsigned long long* dtmin, double cfl, 
   return hipGetLastError();
 }
 
-hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s) {
-  hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, s, p, v);
+hipError_t launch_set_u64(unsigned long long* p, unsigned long long v, int n, hipStream_t s) {
+  hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, s, p, v, n);
   return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ struct StageArgs {
   double alpha;
   int mode;
   unsigned long long* dtmin;  // non-null: reduce Omega/lambda of the new state (bits of a positive double)
+                              // into DT_SLOTS slots
   double* dtloc;         // non-null: local time steps, packed per cell; read for the update and, with
                          // dtmin, overwritten by cfl * Omega/lambda of the new state
   double cfl;
@@ -723,7 +724,7 @@ stage_kernel(StageArgs a) {
     if (tid == 0) {
       double m = sred[0];
       for (int w = 1; w < NT / 64; ++w) m = fmin(m, sred[w]);
-      atomicMin(a.dtmin, (unsigned long long)__double_as_longlong(m));
+      atomicMin(a.dtmin + blockIdx.x % DT_SLOTS, (unsigned long long)__double_as_longlong(m));
     }
   }
 }
