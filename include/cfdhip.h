@@ -301,10 +301,10 @@ cfd_status cfd_set_exec(cfd_ctx* ctx, int mode, int use_graph);
  * receiver ghost is copied straight from the donor's interior in the same
  * launch as the physical patches (all blocks are on this GPU; Sec. 5 fills
  * self-connected ghosts by copying); along an axis that a block connects to
- * itself end to end without reorientation the stage kernel reads the
- * periodic neighbours through the wrap, so between the stages of an inviscid
- * step those connections are not filled at all (every other reader of the
- * ghosts fills them in full).  CFD_GHOSTS_PACKED: the donor strips are
+ * itself end to end without reorientation the stage kernel and the viscous
+ * pass read the periodic neighbours through the wrap, so between the stages
+ * of a step those connections are not filled at all (unless the limiter is
+ * frozen; every other reader of the ghosts fills them in full).  CFD_GHOSTS_PACKED: the donor strips are
  * packed into per-connection segments of the exchange buffer, then unpacked
  * into the receivers (Sec. 7.2 V1/V5), the form a transfer between GPUs would
  * take.  Bit-identical results.  CFD_ERR_ARG for another mode. */

@@ -864,6 +864,7 @@ static ViscArgs visc_args(cfd_ctx* c, const double* q) {
   v.gamma = c->cfg.gamma;
   v.tiles = c->dptr<TileDev>(c->off_vistiles);
   v.ntiles = (int)c->vis_tiles.size();
+  v.wrap = 1;
   return v;
 }
 
@@ -1033,7 +1034,8 @@ static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil
 
 // Ghost fill of state buffer q and, for the Navier-Stokes equations, the
 // viscous residual of q that the next stage-kernel launch subtracts.
-// stencil_only: q is read by the stage kernel alone (see fill_ghosts).
+// stencil_only: q is read by the stage kernel and the viscous pass alone (see
+// fill_ghosts).
 static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only = false) {
   cfd_status st = fill_ghosts(c, q, s, stencil_only);
   if (st != CFD_OK || !c->viscous) return st;
@@ -1044,10 +1046,10 @@ static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s, bool stencil_
 
 // Fill every ghost layer of state buffer q: pack + physical patches, then
 // unpack (packed mode), or direct copies + physical patches (direct mode).
-// stencil_only (direct mode): q is read by the stage kernel alone, which reads
-// the periodic neighbours of a self-connected axis through the wrap, so those
-// connections are left out (their ghosts keep older values, or NaN with
-// CFD_NAN_GHOSTS).
+// stencil_only (direct mode): q is read by the stage kernel and the viscous
+// pass alone, which read the periodic neighbours of a self-connected axis
+// through the wrap, so those connections are left out (their ghosts keep older
+// values, or NaN with CFD_NAN_GHOSTS).
 static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only) {
   GhostArgs g = ghost_args(c, q);
   const int nb = (int)c->blocks.size();
@@ -1155,7 +1157,7 @@ static cfd_status enqueue_classic4(cfd_ctx* c, hipStream_t s, bool timed) {
   double* buf[5] = {A, c->stB(), c->stC(), c->dptr<double>(c->off_rkD), c->dptr<double>(c->off_rkE)};
   const double alpha[4] = {0.5, 0.5, 1.0, 1.0 / 6.0};
   for (int k = 0; k < 4; ++k) {
-    cfd_status st = stage_prep(c, buf[k], s, !c->viscous && !c->frozen);
+    cfd_status st = stage_prep(c, buf[k], s, !c->frozen);
     if (st != CFD_OK) return st;
     StageArgs a = stage_args(c);
     a.qin = buf[k];
@@ -1213,8 +1215,9 @@ static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
     // (a single stage writes into B and is copied back: the kernel reads its
     // input's neighbours while writing, so it never updates in place)
     double* out = (k == M && M > 1) ? A : ((k % 2) ? Bf : Cf);
-    // (an inviscid, unfrozen step reads its stage inputs in the stage kernel only)
-    cfd_status st = stage_prep(c, in, s, !c->viscous && !c->frozen);
+    // (an unfrozen step reads its stage inputs in the stage kernel and the
+    // viscous pass only, both of which read periodic neighbours through the wrap)
+    cfd_status st = stage_prep(c, in, s, !c->frozen);
     if (st != CFD_OK) return st;
     StageArgs a = stage_args(c);
     a.qin = in;

@@ -36,6 +36,7 @@ struct ViscArgs {
   double gamma;
   const TileDev* tiles;    // tiles of viscous_tile_shape over every block (fused pass)
   int ntiles;
+  int wrap;                // read the state of periodic neighbours through the wrap (BlockDev::wrap)
 };
 
 // Tile shape (cells along i, j and planes along k) of the fused pass; the

@@ -296,23 +296,44 @@ __global__ void __launch_bounds__(VT_X* VT_Y) viscous_tile_kernel(ViscArgs a) {
   constexpr int HC = (NC + NT - 1) / NT, HN = (NN + NT - 1) / NT;
   double pc[HC][8];  // centre, velocity, rho, p
   bool pv[HC];
+  // Along an axis that the block connects to itself end to end, the state of
+  // a ghost cell is read from the interior cell it copies (the same values),
+  // so the fill between stages can leave those connections out; the ghost
+  // cell's centre is still read at the ghost.
+  const int wrap = a.wrap ? B.wrap : 0;
+  auto wrapc = [](int x, int n, bool on) { return on ? (x < 0 ? x + n : (x >= n ? x - n : x)) : x; };
+  // this thread's cell items, the same in every plane of the tile: in-plane
+  // offset of the cell and of the cell whose state it holds, how many of i, j
+  // lie outside the block, and whether the item is in the staged frame
+  int pin[HC], pqin[HC], oxy[HC];
+  bool inb[HC];
+#pragma unroll
+  for (int h = 0; h < HC; ++h) {
+    const int e = tid + h * NT;
+    const int ii = i0 - 1 + e % CX, jj = j0 - 1 + e / CX;
+    oxy[h] = (ii < 0 || ii >= B.ni) + (jj < 0 || jj >= B.nj);
+    inb[h] = e < NC && ii <= B.ni && jj <= B.nj;
+    pin[h] = jj * B.pi + ii;
+    pqin[h] = wrapc(jj, B.nj, wrap & 2) * B.pi + wrapc(ii, B.ni, wrap & 1);
+  }
   auto fetch_cells = [&](int kk) {
+    const int ko = kk < 0 || kk >= B.nk;
+    const long long kp = (long long)kk * cplane, kq = (long long)wrapc(kk, B.nk, wrap & 4) * cplane;
+    const long long kc = (long long)min(max(kk, 0), B.nk - 1) * cplane;
 #pragma unroll
     for (int h = 0; h < HC; ++h) {
-      const int e = tid + h * NT;
-      const int ii = i0 - 1 + e % CX, jj = j0 - 1 + e / CX;
-      const int out = (ii < 0 || ii >= B.ni) + (jj < 0 || jj >= B.nj) + (kk < 0 || kk >= B.nk);
-      pv[h] = e < NC && ii <= B.ni && jj <= B.nj && out <= 1;
+      pv[h] = inb[h] && oxy[h] + ko <= 1;
       // every lane loads (an in-block cell where the item is unused), so no
       // branch join makes the compiler wait for this prefetch early
-      const long long p = pv[h] ? cell_at(ii, jj, kk) : cell_at(0, 0, min(max(kk, 0), B.nk - 1));
+      const long long p = pv[h] ? kp + pin[h] : kc;
+      const long long pq = pv[h] ? kq + pqin[h] : kc;
 #pragma unroll
       for (int x = 0; x < 3; ++x) {
         pc[h][x] = cen[x * vs + p];
-        pc[h][3 + x] = q[(1 + x) * vs + p];
+        pc[h][3 + x] = q[(1 + x) * vs + pq];
       }
-      pc[h][6] = q[p];
-      pc[h][7] = q[4 * vs + p];
+      pc[h][6] = q[pq];
+      pc[h][7] = q[4 * vs + pq];
     }
   };
   auto store_cells = [&](int slot) {
@@ -513,17 +534,21 @@ __global__ void __launch_bounds__(VT2* VT2) viscous_tile2d_kernel(ViscArgs a) {
   const double* q = a.q + B.origin;
   const int E = B.ni + 1;
   const long long nb0 = node_index(B, i0, j0, 0);
+  // (periodic neighbours' state through the wrap, as in the 3D pass)
+  const int wrap = a.wrap ? B.wrap : 0;
+  auto wrapc = [](int x, int n, bool on) { return on ? (x < 0 ? x + n : (x >= n ? x - n : x)) : x; };
 
   for (int e = tid; e < NC; e += NT) {
     const int ii = i0 - 1 + e % CX, jj = j0 - 1 + e / CX;
     const int out = (ii < 0 || ii >= B.ni) + (jj < 0 || jj >= B.nj);
     if (ii <= B.ni && jj <= B.nj && out <= 1) {
       const long long p = jj * B.pi + ii;
+      const long long pq = (long long)wrapc(jj, B.nj, wrap & 2) * B.pi + wrapc(ii, B.ni, wrap & 1);
       sc[0][e] = cen[p];
       sc[1][e] = cen[vs + p];
-      sc[2][e] = q[vs + p];
-      sc[3][e] = q[2 * vs + p];
-      sc[4][e] = a.gamma * q[3 * vs + p] / q[p];
+      sc[2][e] = q[vs + pq];
+      sc[3][e] = q[2 * vs + pq];
+      sc[4][e] = a.gamma * q[3 * vs + pq] / q[pq];
     } else {
 #pragma unroll
       for (int w = 0; w < 5; ++w) sc[w][e] = 0.0;

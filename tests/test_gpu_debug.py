@@ -52,6 +52,8 @@ CASES = {
     "ns_square": lambda: _viscous(synth.jittered_periodic_square(48, 40, seed=3), 0.01),
     "ns_ramp_noslip": lambda: _viscous(synth.compression_ramp(100, 70), 1e-3, noslip=True),
     "ns_char_box3d_noslip": lambda: _viscous(synth.characteristic_box_3d((40, 36, 34), seed=10), 5e-3, noslip=True),
+    # periodic along every axis: the viscous pass reads those neighbours through the wrap
+    "ns_box3d_periodic": lambda: _viscous(synth.jittered_periodic_box(dims=(40, 36, 34), seed=4), 5e-3),
 }
 
 
