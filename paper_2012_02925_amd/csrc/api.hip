@@ -1030,14 +1030,16 @@ static StageArgs stage_args(cfd_ctx* c) {
   return a;
 }
 
-static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only = false);
+static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only = false,
+                              bool* promote = nullptr);
 
 // Ghost fill of state buffer q and, for the Navier-Stokes equations, the
 // viscous residual of q that the next stage-kernel launch subtracts.
 // stencil_only: q is read by the stage kernel and the viscous pass alone (see
-// fill_ghosts).
-static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only = false) {
-  cfd_status st = fill_ghosts(c, q, s, stencil_only);
+// fill_ghosts); promote: see fill_ghosts.
+static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only = false,
+                             bool* promote = nullptr) {
+  cfd_status st = fill_ghosts(c, q, s, stencil_only, promote);
   if (st != CFD_OK || !c->viscous) return st;
   ViscArgs v = visc_args(c, q);
   HIP_TRY(c, launch_viscous(c->dim, v, s));
@@ -1050,9 +1052,21 @@ static cfd_status stage_prep(cfd_ctx* c, double* q, hipStream_t s, bool stencil_
 // pass alone, which read the periodic neighbours of a self-connected axis
 // through the wrap, so those connections are left out (their ghosts keep older
 // values, or NaN with CFD_NAN_GHOSTS).
-static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only) {
+// promote (non-null and true): the first ghost launch also forms the step's
+// time step from the slots (the work of dt_promote_kernel) and *promote is
+// cleared; it stays set when nothing is launched.
+static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil_only, bool* promote) {
   GhostArgs g = ghost_args(c, q);
   const int nb = (int)c->blocks.size();
+  auto launch = [&](int n) -> hipError_t {
+    if (n <= 0 || !promote || !*promote) return launch_ghost(c->dim, g, n, s);
+    GhostArgs gp = g;
+    gp.dt = c->dptr<double>(c->off_dt);
+    gp.dtmin = c->dptr<unsigned long long>(c->off_dtmin);
+    gp.cfl = c->cfg.cfl;
+    *promote = false;
+    return launch_ghost(c->dim, gp, n, s);
+  };
   if (c->cfg.debug_flags & CFD_NAN_GHOSTS) {
     CellArgs n = cell_args(c);
     n.dst = q;
@@ -1065,11 +1079,11 @@ static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil
     if (c->exec_mode == CFD_EXEC_PER_BLOCK) {
       for (int b = 0; b < nb; ++b) {
         g.chunk_begin = begin[b];
-        HIP_TRY(c, launch_ghost(c->dim, g, begin[b + 1] - begin[b], s));
+        HIP_TRY(c, launch(begin[b + 1] - begin[b]));
       }
     } else {
       g.chunk_begin = 0;
-      HIP_TRY(c, launch_ghost(c->dim, g, begin[nb], s));
+      HIP_TRY(c, launch(begin[nb]));
     }
     return CFD_OK;
   }
@@ -1077,19 +1091,19 @@ static cfd_status fill_ghosts(cfd_ctx* c, double* q, hipStream_t s, bool stencil
     g.chunks = c->dptr<ChunkDev>(c->off_chunks1);
     for (int b = 0; b < nb; ++b) {
       g.chunk_begin = c->c1_begin[b];
-      HIP_TRY(c, launch_ghost(c->dim, g, c->c1_begin[b + 1] - c->c1_begin[b], s));
+      HIP_TRY(c, launch(c->c1_begin[b + 1] - c->c1_begin[b]));
     }
     g.chunks = c->dptr<ChunkDev>(c->off_chunks2);
     for (int b = 0; b < nb; ++b) {
       g.chunk_begin = c->c2_begin[b];
-      HIP_TRY(c, launch_ghost(c->dim, g, c->c2_begin[b + 1] - c->c2_begin[b], s));
+      HIP_TRY(c, launch(c->c2_begin[b + 1] - c->c2_begin[b]));
     }
   } else {
     g.chunks = c->dptr<ChunkDev>(c->off_chunks1);
     g.chunk_begin = 0;
-    HIP_TRY(c, launch_ghost(c->dim, g, (int)c->chunks1.size(), s));
+    HIP_TRY(c, launch((int)c->chunks1.size()));
     g.chunks = c->dptr<ChunkDev>(c->off_chunks2);
-    HIP_TRY(c, launch_ghost(c->dim, g, (int)c->chunks2.size(), s));
+    HIP_TRY(c, launch((int)c->chunks2.size()));
   }
   return CFD_OK;
 }
@@ -1147,18 +1161,25 @@ static cfd_status launch_stage_all(cfd_ctx* c, StageArgs a, hipStream_t s, bool 
   return CFD_OK;
 }
 
+// dt <- cfl * (minimum over the time-step slots), slots <- +inf, in a launch of its own
+static hipError_t launch_promote(cfd_ctx* c, hipStream_t s) {
+  return launch_dt_promote(c->dptr<double>(c->off_dt), c->dptr<unsigned long long>(c->off_dtmin), c->cfg.cfl, 1,
+                           nullptr, s);
+}
+
 // Classical fourth-order Runge-Kutta step (CFD_RK_CLASSIC4): the stage kernel
 // writes Y2 = Q - dt/2 R(Q) into B, Y3 = Q - dt/2 R(Y2) into C,
 // Y4 = Q - dt R(Y3) into D and Z = Q - dt/6 R(Y4) into E; the combination
 // kernel forms Q^(n+1) in A, and the next step's Omega/lambda comes from it
 // (the cell time-step kernel, in place of the stage kernel's epilogue).
-static cfd_status enqueue_classic4(cfd_ctx* c, hipStream_t s, bool timed) {
+static cfd_status enqueue_classic4(cfd_ctx* c, hipStream_t s, bool timed, bool promote) {
   double* A = c->stA();
   double* buf[5] = {A, c->stB(), c->stC(), c->dptr<double>(c->off_rkD), c->dptr<double>(c->off_rkE)};
   const double alpha[4] = {0.5, 0.5, 1.0, 1.0 / 6.0};
   for (int k = 0; k < 4; ++k) {
-    cfd_status st = stage_prep(c, buf[k], s, !c->frozen);
+    cfd_status st = stage_prep(c, buf[k], s, !c->frozen, k == 0 ? &promote : nullptr);
     if (st != CFD_OK) return st;
+    if (k == 0 && promote) HIP_TRY(c, launch_promote(c, s));
     StageArgs a = stage_args(c);
     a.qin = buf[k];
     a.q0 = A;
@@ -1202,10 +1223,11 @@ static cfd_status enqueue_classic4(cfd_ctx* c, hipStream_t s, bool timed) {
 // Enqueue one full Runge-Kutta step on stream s.
 static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
   const bool cfl = c->cfg.dt_mode != CFD_DT_FIXED;
-  if (cfl)
-    HIP_TRY(c, launch_dt_promote(c->dptr<double>(c->off_dt), c->dptr<unsigned long long>(c->off_dtmin), c->cfg.cfl, 1,
-                                 nullptr, s));
-  if (c->cfg.rk_scheme == CFD_RK_CLASSIC4) return enqueue_classic4(c, s, timed);
+  // (with the CFL step, the previous step's minimum becomes this step's dt in
+  // the first ghost launch, or in its own launch when the first stage input
+  // needs no ghost fill; either way before the first stage kernel)
+  bool promote = cfl;
+  if (c->cfg.rk_scheme == CFD_RK_CLASSIC4) return enqueue_classic4(c, s, timed, promote);
   const int M = c->cfg.rk_stages;
   double* A = c->stA();
   double* Bf = c->stB();
@@ -1217,8 +1239,9 @@ static cfd_status enqueue_step(cfd_ctx* c, hipStream_t s, bool timed) {
     double* out = (k == M && M > 1) ? A : ((k % 2) ? Bf : Cf);
     // (an unfrozen step reads its stage inputs in the stage kernel and the
     // viscous pass only, both of which read periodic neighbours through the wrap)
-    cfd_status st = stage_prep(c, in, s, !c->frozen);
+    cfd_status st = stage_prep(c, in, s, !c->frozen, k == 1 ? &promote : nullptr);
     if (st != CFD_OK) return st;
+    if (k == 1 && promote) HIP_TRY(c, launch_promote(c, s));
     StageArgs a = stage_args(c);
     a.qin = in;
     a.q0 = A;

@@ -21,6 +21,12 @@ struct GhostArgs {
   const double* bcparams;  // boundary parameters, MAXV doubles per parameter slot
   const double* metric;
   Gas gas;
+  // non-null: the first wavefront of workgroup 0 also forms the time step,
+  // dt <- cfl * min over the DT_SLOTS slots, slots <- +inf (the promote of a
+  // step folded into its first ghost launch)
+  double* dt;
+  unsigned long long* dtmin;
+  double cfl;
 };
 
 struct CellArgs {

@@ -103,10 +103,28 @@ __device__ void subsonic_outflow_state(double* g, const double* n, double pback,
   if (Vi < sqrt(gs.gamma * g[NV - 1] / g[0])) g[NV - 1] = pback;
 }
 
+// dt <- cfl * min over the DT_SLOTS slots (when promote); slots <- +inf.
+// Called by one whole wavefront (lanes 0..63): every lane reads one slot, the
+// minimum is formed by shuffles, and each lane resets its own slot after that.
+__device__ __forceinline__ void promote_slots(double* dt, unsigned long long* dtmin, double cfl, int promote,
+                                              double* out) {
+  static_assert(DT_SLOTS == 64, "one slot per lane of the wavefront");
+  const int t = threadIdx.x;
+  double m = __longlong_as_double((long long)dtmin[t]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
+  if (t == 0) {
+    if (promote) dt[0] = cfl * m;
+    if (out) out[0] = cfl * m;
+  }
+  if (promote) dtmin[t] = (unsigned long long)__double_as_longlong(INFINITY);
+}
+
 template <int DIM>
 __global__ void __launch_bounds__(CHUNK) ghost_kernel(GhostArgs a) {
   constexpr int NV = DIM + 2;
   using ML = MetricLayout<DIM>;
+  if (a.dtmin && blockIdx.x == 0 && threadIdx.x < 64) promote_slots(a.dt, a.dtmin, a.cfl, 1, nullptr);
   const ChunkDev ch = a.chunks[a.chunk_begin + blockIdx.x];
   const int e = ch.start + threadIdx.x;
   if (threadIdx.x >= ch.count) return;
@@ -328,21 +346,9 @@ __global__ void __launch_bounds__(256) cell_dt_kernel(CellArgs a) {
   }
 }
 
-// dt <- cfl * min over the DT_SLOTS slots (when promote); slots <- +inf.
-// One wavefront: every lane reads one slot, the minimum is formed by
-// shuffles, and each lane resets its own slot after that.
 __global__ void __launch_bounds__(64) dt_promote_kernel(double* dt, unsigned long long* dtmin, double cfl, int promote,
                                                         double* out) {
-  static_assert(DT_SLOTS == 64, "one slot per lane of the wavefront");
-  const int t = threadIdx.x;
-  double m = __longlong_as_double((long long)dtmin[t]);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
-  if (t == 0) {
-    if (promote) dt[0] = cfl * m;
-    if (out) out[0] = cfl * m;
-  }
-  if (promote) dtmin[t] = (unsigned long long)__double_as_longlong(INFINITY);
+  promote_slots(dt, dtmin, cfl, promote, out);
 }
 
 __global__ void set_u64_kernel(unsigned long long* p, unsigned long long v, int n) {
