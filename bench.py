@@ -285,7 +285,7 @@ def bench_ramp(n=1024, steps=10, warmup=3):
     return out
 
 
-def bench_navier_stokes(workload, n, variant, steps=5, warmup=2, reynolds=1.0e4):
+def bench_navier_stokes(workload, n, variant, steps=20, warmup=5, reynolds=1.0e4):
     """Same workload and tiles as the headline with the laminar viscous terms
     switched on (mu = M / Re per unit length): whole RK steps timed with
     events on the library stream (captured step), against the Euler step; the
@@ -535,7 +535,7 @@ def main():
         out["ramp_2d"] = bench_ramp()
         print("[bench] laminar Navier-Stokes vs Euler on the same workload", file=sys.stderr, flush=True)
         out["navier_stokes"] = bench_navier_stokes(args.workload, args.n, out["config"]["tile_variant"])
-        out["navier_stokes_2d"] = bench_navier_stokes("compression_ramp", 1024, 2, steps=10, warmup=3)
+        out["navier_stokes_2d"] = bench_navier_stokes("compression_ramp", 1024, 2, steps=50, warmup=10)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
